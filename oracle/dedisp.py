@@ -1,0 +1,34 @@
+"""Brute-force incoherent dedispersion (the paper's dedispersion phase, section 2.1).
+
+Definition: D[d][t] = sum over c < nchan of X[c][t + s[d][c]], for 0 <= t < n_out,
+where n_out = n_in - maxshift. X is uint8 and D is accumulated exactly in int64.
+A DM-0 trial has all shifts 0, so it is the plain channel sum.
+"""
+
+import numpy as np
+
+
+def dedisperse(x: np.ndarray, shifts: np.ndarray, n_in: int | None = None, maxshift: int | None = None) -> np.ndarray:
+    """All DM rows. `x` is uint8 [nchan, >= n_in], `shifts` int [ndm, nchan]."""
+    return dedisperse_rows(x, shifts, range(shifts.shape[0]), n_in, maxshift)
+
+
+def dedisperse_rows(x: np.ndarray, shifts: np.ndarray, rows, n_in: int | None = None,
+                    maxshift: int | None = None) -> np.ndarray:
+    """Only the DM rows listed in `rows`, in that order. Returns int64 [len(rows), n_out]."""
+    nchan = shifts.shape[1]
+    if x.shape[0] < nchan:
+        raise ValueError("input has fewer channels than the shift table")
+    n_in = x.shape[1] if n_in is None else n_in
+    m = int(shifts.max()) if maxshift is None else maxshift
+    n_out = n_in - m
+    if n_out < 1:
+        raise ValueError("input shorter than maxshift + 1")
+    rows = list(rows)
+    out = np.zeros((len(rows), n_out), dtype=np.int64)
+    for i, d in enumerate(rows):
+        acc = out[i]
+        for c in range(nchan):
+            s = int(shifts[d, c])
+            acc += x[c, s:s + n_out]
+    return out
