@@ -1,0 +1,161 @@
+/*
+ * aa.h - C ABI of the MI355X (gfx950) dedispersion + single-pulse-search library.
+ *
+ * The library implements the GPU phase of the pipeline studied in Novotny, Adamek
+ * and Armour, "Implementing CUDA Streams into AstroAccelerate - A Case Study":
+ * the dedispersion phase (section 2.1) and the single-pulse search (section 2.2).
+ * Both run over time chunks that are split across streams (section 1, Fig. 2).
+ * The five-step streams recipe of section 2 shapes the pipeline calls: create
+ * streams, pin host memory, use asynchronous copies, tag kernels and copies with
+ * a stream, and take every synchronisation off the hot loop.
+ *
+ * Conventions for every call:
+ *  - The return value is a status code (AA_OK, or one of the codes below). No
+ *    C++ exception crosses this boundary. aa_last_error() returns a message for
+ *    the last failing call on the calling thread.
+ *  - "d_" pointers are device (HBM) pointers and "h_" pointers are host pointers.
+ *    A stream argument is a hipStream_t passed as void*. NULL means the null stream.
+ *  - Compute calls are asynchronous on the given stream. The caller owns every
+ *    buffer it passes and must keep it alive until the stream has finished with it.
+ *  - Numeric definitions (shift rounding, statistics, S/N rounding points, the peak
+ *    rule) are those stated for aa_plan and aa_single_pulse below.
+ */
+#ifndef AA_H
+#define AA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+#define AA_OK         0
+#define AA_EAGAIN     1    /* nothing ready yet (aa_poll)                         */
+#define AA_EINVAL    (-1)  /* invalid argument or descriptor                      */
+#define AA_ESHORT    (-2)  /* too few samples for maxshift + widest boxcar        */
+#define AA_ENOMEM    (-3)  /* host or device allocation failed                    */
+#define AA_EHIP      (-4)  /* a HIP runtime call failed (message in aa_last_error) */
+#define AA_EOVERFLOW (-5)  /* more candidates than capacity; the true count is kept */
+#define AA_EBUSY     (-6)  /* admission refused: no free slot or HBM budget       */
+
+const char* aa_last_error(void);
+const char* aa_version(void);
+
+/* ---- plan (A0) ------------------------------------------------------------
+ * Section 1 places "mapping tasks to resources and allocation of all necessary
+ * memory" before the search, and section 2.2 moves the search's allocations
+ * there. A plan fixes everything that does not depend on the data:
+ *   f_c      = f_top - c * foff                  (channel 0 is the highest)
+ *   s[d][c]  = floor(((K * dm[d]) * (1/(f_c*f_c) - 1/(f_top*f_top))) / tsamp + 0.5)
+ *              K = 4.148808e3 MHz^2 s pc^-1 cm^3. Each step is one IEEE float64
+ *              operation in this order, with no fused multiply-add, on the host.
+ *   maxshift M = max s;  N_dd = nsamp - M;  T = N_dd - wmax + 1 boxcar starts.
+ * On success the plan holds host and device copies of s (int32 [ndm][nchan]).
+ * The device copy is uploaded once, to the device current at aa_plan time,
+ * unless AA_PLAN_HOST_ONLY is set. A plan is immutable and may be shared between
+ * threads.
+ * Errors: AA_EINVAL for nchan < 1, ndm < 1, DMs that are negative or not
+ * ascending, f_top - (nchan-1)*foff <= 0, foff <= 0, tsamp <= 0, widths that are
+ * not ascending, unique and >= 1, wmax > AA_MAX_WIDTH, nchan*255*wmax >= 2^32
+ * (boxcar sums are exact 32-bit integers), a stat block that is not a positive
+ * multiple of 256 or that could overflow int64 moments, or a threshold that is not
+ * finite. AA_ESHORT if T < 1. AA_EHIP or AA_ENOMEM if the upload fails.
+ */
+#define AA_PLAN_HOST_ONLY 1u
+#define AA_MAX_WIDTH      1024
+#define AA_MAX_NCHAN      65535
+
+typedef struct aa_plan_s* aa_plan_t;
+
+typedef struct {
+    int32_t       nchan;          /* channels (rows of the filterbank)               */
+    int64_t       nsamp;          /* samples per channel of a whole-signal call      */
+    double        f_top_mhz;      /* centre frequency of channel 0 (highest), MHz   */
+    double        foff_mhz;       /* channel width, MHz, > 0                         */
+    double        tsamp_s;        /* sampling time, s                                */
+    const double* dm;             /* ndm trials, pc cm^-3, ascending, >= 0 (copied)  */
+    int32_t       ndm;
+    const int32_t* widths;        /* boxcar widths in samples, ascending (copied)    */
+    int32_t       nwidths;
+    float         snr_threshold;  /* candidates need best S/N >= threshold           */
+    int32_t       stat_block;     /* starts per statistics block; 0 means 32768      */
+    uint32_t      flags;          /* AA_PLAN_HOST_ONLY                               */
+} aa_plan_desc_t;
+
+typedef struct {
+    int32_t nchan, ndm, nwidths, wmax;
+    int64_t nsamp, maxshift, n_dd, n_start, stat_block, nblocks;
+    int64_t in_pitch;       /* recommended input row pitch (bytes): nsamp rounded up to 256 */
+    int64_t out_pitch;      /* recommended plane row pitch (elements): n_dd rounded to 64   */
+    size_t  work_bytes;     /* aa_single_pulse scratch for a whole-signal call             */
+    int32_t device;         /* device of the uploaded shift table, -1 for host-only         */
+} aa_plan_info_t;
+
+int aa_plan(const aa_plan_desc_t* desc, aa_plan_t* out);
+int aa_plan_info(aa_plan_t plan, aa_plan_info_t* out);
+/* Copies the int32 shift table, ndm*nchan entries, row-major [d][c], to h_out. */
+int aa_plan_shifts(aa_plan_t plan, int32_t* h_out);
+void aa_plan_destroy(aa_plan_t plan);
+
+/* ---- dedispersion (A2) -----------------------------------------------------
+ * Section 2.1 (dedispersion phase). Brute-force incoherent dedispersion:
+ *   d_out[d * out_pitch + t] = sum over c < nchan of d_in[c * in_pitch + t + s[d][c]]
+ * for 0 <= d < ndm and 0 <= t < n_in - maxshift. Sums are exact int32: at most
+ * 65535 * 255 < 2^31.
+ * d_in:  uint8 [nchan][in_pitch]. Samples 0..n_in-1 of each row are read.
+ *        d_in and in_pitch must be multiples of 16 bytes.
+ * n_in:  valid samples per row. maxshift + 1 <= n_in <= in_pitch.
+ * d_out: int32 [ndm][out_pitch], out_pitch >= n_in - maxshift, 16-byte aligned rows.
+ *        Columns >= n_in - maxshift are not written.
+ * Errors: AA_EINVAL on a host-only plan, bad sizes or misaligned pointers.
+ * AA_EHIP if the launch fails.
+ */
+int aa_dedisperse(aa_plan_t plan, const uint8_t* d_in, int64_t in_pitch, int64_t n_in,
+                  int32_t* d_out, int64_t out_pitch, void* stream);
+
+/* ---- single-pulse search (A3-A5) -------------------------------------------
+ * Section 2.2 (single-pulse search phase). Input: a dedispersed plane whose column
+ * j holds absolute start dd_t0 + j, valid for j < dd_n. Output: the candidates
+ * among the starts [t_begin, t_end).
+ *   - Statistics per DM row and per block of stat_block starts, aligned to absolute
+ *     start 0. n, S1 and S2 are exact. mu = S1/n.
+ *     var = double(n*S2 - S1^2) / double(n*n), where the integer is exact and is
+ *     rounded once. sigma = sqrt(var).
+ *     wmu_w = w*mu. r_w = 1/(sigma*sqrt(w)), or 0 if sigma == 0.
+ *   - S/N(d,t,w) = (double(sum_{i<w} D[d][t+i]) - wmu_w) * r_w. best = max over w,
+ *     and wbest is the smallest width that attains it.
+ *   - (d,t) is a candidate iff best >= threshold and best is a 3x3 maximum in
+ *     (d, t): strictly greater than the neighbours earlier in row-major order, and
+ *     >= the later ones. Neighbours outside [0,ndm) x [0,t_total) are ignored. The
+ *     whole window uses the statistics of the centre's block.
+ * t_begin must be a multiple of stat_block. t_end - t_begin >= 1.
+ * t_total is the T of the whole signal, or -1 if it is not known yet. The plane
+ * must hold the column t_begin-1 (if t_begin > 0) and every column up to
+ * right + wmax - 2, where right = t_end if t_end == t_total, else t_end + 1.
+ * d_work:  scratch of at least aa_single_pulse_work_bytes(plan, t_end - t_begin).
+ * d_cand:  aa_candidate_t [cap], written in (dm_idx, t) order with beam = 0.
+ * d_count: one int32. It receives the true number of candidates. If that exceeds
+ *          cap, only the first cap are written (AA_EOVERFLOW is seen by the caller
+ *          when it reads *d_count > cap).
+ * d_best:  optional float [ndm][best_pitch] of float(best) for t in [t_begin, t_end).
+ */
+typedef struct {
+    int32_t dm_idx;
+    int32_t width;
+    int64_t t;        /* absolute start sample of the boxcar */
+    float   snr;
+    int32_t beam;
+} aa_candidate_t;
+
+int aa_single_pulse_work_bytes(aa_plan_t plan, int64_t n_starts, size_t* out);
+int aa_single_pulse(aa_plan_t plan, const int32_t* d_dd, int64_t dd_pitch, int64_t dd_t0,
+                    int64_t dd_n, int64_t t_begin, int64_t t_end, int64_t t_total,
+                    void* d_work, size_t work_bytes, aa_candidate_t* d_cand, int32_t cap,
+                    int32_t* d_count, float* d_best, int64_t best_pitch, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AA_H */

@@ -1,7 +1,8 @@
 """Brute-force incoherent dedispersion (the paper's dedispersion phase, section 2.1).
 
 Definition: D[d][t] = sum over c < nchan of X[c][t + s[d][c]], for 0 <= t < n_out,
-where n_out = n_in - maxshift. X is uint8 and D is accumulated exactly in int64.
+where n_out = n_in - maxshift. X is uint8. D is accumulated exactly in int32, since
+at most 65535 * 255 < 2^31, and returned as int64.
 A DM-0 trial has all shifts 0, so it is the plain channel sum.
 """
 
@@ -25,10 +26,14 @@ def dedisperse_rows(x: np.ndarray, shifts: np.ndarray, rows, n_in: int | None = 
     if n_out < 1:
         raise ValueError("input shorter than maxshift + 1")
     rows = list(rows)
+    if nchan > 65535:
+        raise ValueError("more than 65535 channels could overflow int32 sums")
     out = np.zeros((len(rows), n_out), dtype=np.int64)
+    acc = np.zeros(n_out, dtype=np.int32)
     for i, d in enumerate(rows):
-        acc = out[i]
+        acc[:] = 0
         for c in range(nchan):
             s = int(shifts[d, c])
-            acc += x[c, s:s + n_out]
+            np.add(acc, x[c, s:s + n_out], out=acc)
+        out[i] = acc
     return out

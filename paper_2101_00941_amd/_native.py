@@ -1,0 +1,83 @@
+"""ctypes view of the C ABI in include/aa.h. Argument marshalling only.
+
+Importing this module loads the in-tree libaa_mi355x.so. If the library has not
+been built, it raises ImportError. There is no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libaa_mi355x.so")
+
+AA_OK, AA_EAGAIN, AA_EINVAL, AA_ESHORT, AA_ENOMEM, AA_EHIP, AA_EOVERFLOW, AA_EBUSY = 0, 1, -1, -2, -3, -4, -5, -6
+AA_PLAN_HOST_ONLY = 1
+STATUS_NAMES = {0: "AA_OK", 1: "AA_EAGAIN", -1: "AA_EINVAL", -2: "AA_ESHORT", -3: "AA_ENOMEM",
+                -4: "AA_EHIP", -5: "AA_EOVERFLOW", -6: "AA_EBUSY"}
+
+CANDIDATE_DTYPE = np.dtype([("dm_idx", "<i4"), ("width", "<i4"), ("t", "<i8"), ("snr", "<f4"), ("beam", "<i4")])
+assert CANDIDATE_DTYPE.itemsize == 24
+
+
+class PlanDesc(C.Structure):
+    _fields_ = [("nchan", C.c_int32), ("nsamp", C.c_int64), ("f_top_mhz", C.c_double),
+                ("foff_mhz", C.c_double), ("tsamp_s", C.c_double), ("dm", C.POINTER(C.c_double)),
+                ("ndm", C.c_int32), ("widths", C.POINTER(C.c_int32)), ("nwidths", C.c_int32),
+                ("snr_threshold", C.c_float), ("stat_block", C.c_int32), ("flags", C.c_uint32)]
+
+
+class PlanInfo(C.Structure):
+    _fields_ = [("nchan", C.c_int32), ("ndm", C.c_int32), ("nwidths", C.c_int32), ("wmax", C.c_int32),
+                ("nsamp", C.c_int64), ("maxshift", C.c_int64), ("n_dd", C.c_int64), ("n_start", C.c_int64),
+                ("stat_block", C.c_int64), ("nblocks", C.c_int64), ("in_pitch", C.c_int64),
+                ("out_pitch", C.c_int64), ("work_bytes", C.c_size_t), ("device", C.c_int32)]
+
+
+class AAError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2101_00941_amd.build` "
+                          "(or __graft_entry__.build())")
+    # One HIP runtime per process: PyTorch ships its own libamdhip64.so.7. Loading torch
+    # first makes the library's libamdhip64.so.7 dependency bind to that same copy
+    # (same soname), instead of mapping a second runtime from /opt/rocm.
+    import torch  # noqa: F401
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+    sig = {
+        "aa_last_error": (C.c_char_p, []),
+        "aa_version": (C.c_char_p, []),
+        "aa_plan": (C.c_int, [C.POINTER(PlanDesc), C.POINTER(vp)]),
+        "aa_plan_info": (C.c_int, [vp, C.POINTER(PlanInfo)]),
+        "aa_plan_shifts": (C.c_int, [vp, vp]),
+        "aa_plan_destroy": (None, [vp]),
+        "aa_dedisperse": (C.c_int, [vp, vp, i64, i64, vp, i64, vp]),
+        "aa_single_pulse_work_bytes": (C.c_int, [vp, i64, C.POINTER(sz)]),
+        "aa_single_pulse": (C.c_int, [vp, vp, i64, i64, i64, i64, i64, i64, vp, sz, vp, i32, vp, vp, i64, vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def check(rc: int) -> int:
+    if rc < 0:
+        raise AAError(rc, lib().aa_last_error().decode())
+    return rc

@@ -1,0 +1,162 @@
+"""Python binding with the C ABI's names. It marshals arguments only.
+
+PyTorch supplies device memory and streams: torch.cuda tensors are passed by
+pointer, and the current torch stream, or the one given, is passed as a
+hipStream_t. Every step of the computation runs in the HIP library.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _native as N
+
+
+def _stream_handle(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """aa_plan: float64 shift table, sizes and the one-time device upload."""
+
+    def __init__(self, nchan, nsamp, f_top, foff, tsamp, dms, widths, threshold, stat_block=0, host_only=False):
+        L = N.lib()
+        self._dm = np.ascontiguousarray(np.asarray(dms, dtype=np.float64))
+        self._w = np.ascontiguousarray(np.asarray(widths, dtype=np.int32))
+        d = N.PlanDesc()
+        d.nchan = int(nchan)
+        d.nsamp = int(nsamp)
+        d.f_top_mhz = float(f_top)
+        d.foff_mhz = float(foff)
+        d.tsamp_s = float(tsamp)
+        d.dm = self._dm.ctypes.data_as(C.POINTER(C.c_double))
+        d.ndm = len(self._dm)
+        d.widths = self._w.ctypes.data_as(C.POINTER(C.c_int32))
+        d.nwidths = len(self._w)
+        d.snr_threshold = float(threshold)
+        d.stat_block = int(stat_block)
+        d.flags = N.AA_PLAN_HOST_ONLY if host_only else 0
+        h = C.c_void_p()
+        N.check(L.aa_plan(C.byref(d), C.byref(h)))
+        self._h = h
+        inf = N.PlanInfo()
+        N.check(L.aa_plan_info(h, C.byref(inf)))
+        self.info = {k: getattr(inf, k) for k, _ in N.PlanInfo._fields_}
+        self.threshold = float(np.float32(threshold))
+        self.widths = [int(x) for x in self._w]
+        self.dms = self._dm.copy()
+
+    @classmethod
+    def from_workload(cls, w, **kw):
+        return cls(w["nchan"], w["nsamp"], w["f_top"], w["foff"], w["tsamp"], w["dms"], w["widths"],
+                   w["threshold"], w.get("stat_block", 0), **kw)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __getattr__(self, k):
+        info = self.__dict__.get("info")
+        if info is not None and k in info:
+            return info[k]
+        raise AttributeError(k)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            N.lib().aa_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def shifts(self) -> np.ndarray:
+        out = np.empty((self.info["ndm"], self.info["nchan"]), dtype=np.int32)
+        N.check(N.lib().aa_plan_shifts(self._h, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    # ---- compute -------------------------------------------------------------
+    def dedisperse(self, x, n_in=None, out=None, stream=None):
+        """aa_dedisperse. x: uint8 CUDA tensor [nchan, in_pitch]. Returns int32 [ndm, out_pitch]."""
+        import torch
+        if x.dtype != torch.uint8 or not x.is_cuda or x.dim() != 2 or not x.is_contiguous():
+            raise ValueError("x must be a contiguous uint8 CUDA tensor [nchan, pitch]")
+        if x.shape[0] < self.info["nchan"]:
+            raise ValueError("x has fewer rows than the plan has channels")
+        n_in = x.shape[1] if n_in is None else int(n_in)
+        if n_in > x.shape[1]:
+            raise ValueError("n_in exceeds the row length of x")
+        n_out = n_in - self.info["maxshift"]
+        if out is None:
+            pitch = (max(n_out, 1) + 63) // 64 * 64
+            out = torch.empty((self.info["ndm"], pitch), dtype=torch.int32, device=x.device)
+        elif (out.dtype != torch.int32 or out.dim() != 2 or out.shape[0] < self.info["ndm"]
+              or out.shape[1] < n_out or out.stride(1) != 1):
+            raise ValueError("out must be int32 [ndm, >= n_out] with unit column stride")
+        N.check(N.lib().aa_dedisperse(self._h, _ptr(x), x.stride(0), n_in, _ptr(out), out.stride(0),
+                                      _stream_handle(stream)))
+        return out
+
+    def work_bytes(self, n_starts):
+        v = C.c_size_t()
+        N.check(N.lib().aa_single_pulse_work_bytes(self._h, int(n_starts), C.byref(v)))
+        return v.value
+
+    def single_pulse(self, dd, dd_t0=0, dd_n=None, t_begin=0, t_end=None, t_total=None, cap=1 << 16,
+                     want_best=False, work=None, cand=None, count=None, stream=None):
+        """aa_single_pulse. Returns (cand uint8 [cap*24] tensor, count int32 [1] tensor, best or None).
+
+        Use `candidates_to_numpy(cand, count)` after the stream has finished.
+        """
+        import torch
+        if dd.dtype != torch.int32 or not dd.is_cuda or dd.dim() != 2:
+            raise ValueError("dd must be an int32 CUDA tensor [ndm, pitch]")
+        if dd.shape[0] < self.info["ndm"] or dd.stride(1) != 1:
+            raise ValueError("dd must have ndm rows and unit column stride")
+        dd_n = min(self.info["n_dd"] - dd_t0, dd.shape[1]) if dd_n is None else int(dd_n)
+        if dd_n > dd.shape[1]:
+            raise ValueError("dd_n exceeds the row length of dd")
+        t_end = self.info["n_start"] if t_end is None else int(t_end)
+        t_total = self.info["n_start"] if t_total is None else int(t_total)
+        n = t_end - t_begin
+        wb = self.work_bytes(n)
+        dev = dd.device
+        if work is None or work.numel() < wb:
+            work = torch.empty(wb, dtype=torch.uint8, device=dev)
+        if cand is None:
+            cand = torch.empty(max(cap, 1) * 24, dtype=torch.uint8, device=dev)
+        elif cand.numel() < cap * 24 or cand.dtype != torch.uint8:
+            raise ValueError("cand must be a uint8 buffer of at least cap * 24 bytes")
+        if count is None:
+            count = torch.zeros(1, dtype=torch.int32, device=dev)
+        best = None
+        if want_best:
+            best = torch.empty((self.info["ndm"], (n + 63) // 64 * 64), dtype=torch.float32, device=dev)
+        N.check(N.lib().aa_single_pulse(self._h, _ptr(dd), dd.stride(0), int(dd_t0), dd_n, int(t_begin), t_end,
+                                        t_total, _ptr(work), work.numel(), _ptr(cand), int(cap), _ptr(count),
+                                        _ptr(best) if best is not None else None,
+                                        best.stride(0) if best is not None else 0, _stream_handle(stream)))
+        return cand, count, best
+
+
+def candidates_to_numpy(cand, count, cap=None):
+    """Copy a candidate buffer to the host as a structured array (dm_idx, width, t, snr, beam)."""
+    n = int(count.item()) if hasattr(count, "item") else int(count)
+    cap = cand.numel() // 24 if cap is None else cap
+    n = min(n, cap)
+    raw = cand[: n * 24].cpu().numpy()
+    return raw.view(N.CANDIDATE_DTYPE).copy()
+
+
+def candidates_as_tuples(arr):
+    return [(int(r["dm_idx"]), int(r["t"]), int(r["width"]), float(r["snr"])) for r in arr]

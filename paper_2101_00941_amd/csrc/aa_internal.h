@@ -1,0 +1,81 @@
+// Internal declarations shared by the host runtime and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/aa.h"
+
+namespace aa {
+
+// Thread-local error message behind aa_last_error().
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define AA_HIP(call)                                         \
+    do {                                                     \
+        hipError_t aa_e_ = (call);                           \
+        if (aa_e_ != hipSuccess) return ::aa::hip_fail(aa_e_, #call); \
+    } while (0)
+
+// Dedispersion tiling (compile-time shape of the kernel). A work-group of
+// kDedispWaves waves covers one DM block (up to kDedispWaves * kDmPerWave trials)
+// and one time tile of 64 * kSampPerLane samples. Each channel pass stages
+// kChanPerPass input rows in LDS.
+constexpr int kSampPerLane = 16;
+constexpr int kDmPerWave = 4;
+constexpr int kDedispWaves = 4;
+constexpr int kChanPerPass = 16;
+constexpr int kTimeTile = 64 * kSampPerLane;
+constexpr int kDmBlock = kDedispWaves * kDmPerWave;
+constexpr int kMaxRowBytes = 1664;   // LDS row length limit for one staged channel row
+
+// Single-pulse-search tiling: a work-group covers kSpsRows DM rows and kSpsTile starts.
+constexpr int kSpsTile = 256;
+constexpr int kSpsRows = 8;
+
+struct DmBlock {
+    int32_t first;   // first DM trial of the block
+    int32_t count;   // trials in the block (<= kDmBlock)
+    int32_t row;     // LDS row length (bytes) the block needs, multiple of 16
+    int32_t pad;
+};
+
+}  // namespace aa
+
+struct aa_plan_s {
+    int32_t nchan = 0, ndm = 0, nwidths = 0, wmax = 0, stat_block = 0;
+    int64_t nsamp = 0, maxshift = 0, n_dd = 0, n_start = 0, nblocks = 0;
+    double f_top = 0, foff = 0, tsamp = 0;
+    float threshold = 0;
+    uint32_t flags = 0;
+    std::vector<double> dm;
+    std::vector<int32_t> widths;
+    std::vector<double> sqrtw;            // sqrt(double(w)), rounded once on the host
+    std::vector<int32_t> shifts;          // [ndm][nchan]
+    // dedispersion tiling tables
+    std::vector<aa::DmBlock> blocks;
+    std::vector<int32_t> offs;            // [ndm][nchan]: s[d][c] - (s[first][c] & ~15)
+    int32_t max_row = 0;
+    // device copies (uploaded once at plan time)
+    int device = -1;
+    int32_t* d_shifts = nullptr;
+    int32_t* d_offs = nullptr;
+    aa::DmBlock* d_blocks = nullptr;
+    int32_t* d_widths = nullptr;
+};
+
+namespace aa {
+// Launchers (dedisp.hip, sps.hip). Arguments are validated by the callers.
+int launch_dedisperse(const aa_plan_s* p, const uint8_t* d_in, int64_t in_pitch, int64_t n_in,
+                      int32_t* d_out, int64_t out_pitch, hipStream_t stream);
+size_t sps_work_bytes(const aa_plan_s* p, int64_t n_starts);
+int launch_single_pulse(const aa_plan_s* p, const int32_t* d_dd, int64_t dd_pitch, int64_t dd_t0,
+                        int64_t dd_n, int64_t t_begin, int64_t t_end, int64_t t_total, void* d_work,
+                        aa_candidate_t* d_cand, int32_t cap, int32_t* d_count, float* d_best,
+                        int64_t best_pitch, hipStream_t stream);
+}  // namespace aa

@@ -1,0 +1,362 @@
+// Single-pulse search on a dedispersed plane, for gfx950 (the paper's SPDT phase,
+// section 2.2). Three kernels run in order on the caller's stream:
+//   sps_stats   exact int64 moments per (DM row, stat block), then mu and sigma in
+//               float64, then the per-width normalisation wmu_w = w*mu and
+//               r_w = 1/(sigma*sqrt(w)).
+//   sps_detect  per (8 DM rows, 256 starts) tile: LDS prefix sums give the boxcars,
+//               best S/N is taken over widths in float64, and a 3x3 peak test runs on
+//               a one-sample, one-row halo. The result is a bit mask of candidates
+//               per row, plus integer per-row counts.
+//   sps_emit    one work-group per DM row. The row's output offset is the sum of
+//               the counts of the rows before it. A block scan of the mask ranks each
+//               candidate, and the candidate is written in (dm, t) order. Its S/N and
+//               width are recomputed with the same float64 operations.
+// No float atomics and no cross-stream waits are involved. The only atomics are
+// integer counter adds, and their sum does not depend on order. Output order comes
+// from the scan, not from the atomics. The paper's section 2.2 notes that its
+// streamed search stalled on atomics combined with event waits.
+#pragma clang fp contract(off)
+
+#include "aa_internal.h"
+#include "numerics.h"
+
+namespace aa {
+namespace {
+
+constexpr int kMaxWidths = 32;
+
+struct SpsConst {
+    int32_t nw;
+    int32_t wmax;
+    int32_t widths[kMaxWidths];
+    double sqrtw[kMaxWidths];
+};
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// ---- statistics -------------------------------------------------------------
+__global__ __launch_bounds__(256) void sps_stats_kernel(const int32_t* __restrict__ dd, int64_t dd_pitch,
+                                                        int64_t dd_t0, int64_t t_begin, int64_t t_end,
+                                                        int32_t B, int32_t ndm, SpsConst sc,
+                                                        double* __restrict__ norms,
+                                                        int32_t* __restrict__ rowcount) {
+    const int j = blockIdx.x;
+    const int d = blockIdx.y;
+    const int64_t lo = t_begin + static_cast<int64_t>(j) * B;
+    const int64_t hi = min(lo + B, t_end);
+    const int32_t* row = dd + static_cast<int64_t>(d) * dd_pitch - dd_t0;
+    uint64_t s1 = 0, s2 = 0;
+    for (int64_t t = lo + threadIdx.x; t < hi; t += 256) {
+        const uint32_t v = static_cast<uint32_t>(row[t]);
+        s1 += v;
+        s2 += static_cast<uint64_t>(v) * v;
+    }
+    s1 = wave_sum_u64(s1);
+    s2 = wave_sum_u64(s2);
+    __shared__ uint64_t part[2][4];
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        part[0][wave] = s1;
+        part[1][wave] = s2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s1 = part[0][0] + part[0][1] + part[0][2] + part[0][3];
+        s2 = part[1][0] + part[1][1] + part[1][2] + part[1][3];
+        const uint64_t n = static_cast<uint64_t>(hi - lo);
+        const double mu = static_cast<double>(s1) / static_cast<double>(n);
+        const unsigned __int128 num = static_cast<unsigned __int128>(n) * s2 -
+                                      static_cast<unsigned __int128>(s1) * s1;
+        const double var = u128_to_double_rn(num) / static_cast<double>(n * n);
+        const double sigma = __builtin_sqrt(var);
+        double* out = norms + (static_cast<int64_t>(j) * ndm + d) * (2 * sc.nw);
+        for (int k = 0; k < sc.nw; ++k) {
+            out[k] = static_cast<double>(sc.widths[k]) * mu;
+            out[sc.nw + k] = sigma == 0.0 ? 0.0 : 1.0 / (sigma * sc.sqrtw[k]);
+        }
+        if (j == 0) rowcount[d] = 0;
+    }
+}
+
+// ---- detection ----------------------------------------------------------------
+constexpr int kHaloRows = kSpsRows + 2;
+constexpr int kHaloCols = kSpsTile + 2;
+
+__global__ __launch_bounds__(256) void sps_detect_kernel(
+    const int32_t* __restrict__ dd, int64_t dd_pitch, int64_t dd_t0, int64_t dd_n, int64_t t_begin,
+    int64_t t_end, int64_t t_total, int32_t B, int32_t ndm, double threshold, SpsConst sc,
+    const double* __restrict__ norms, int32_t* __restrict__ rowcount, uint32_t* __restrict__ mask,
+    int64_t nwords, float* __restrict__ best_out, int64_t best_pitch) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    const int tw = kSpsTile + 1 + sc.wmax;            // D columns t_tile0-1 .. t_tile0+255+wmax
+    const int pw = tw + 1;                            // prefix entries per row
+    double* best = reinterpret_cast<double*>(smem);                      // [kHaloRows][kHaloCols]
+    double* nrm = best + kHaloRows * kHaloCols;                          // [kHaloRows][2*nw]
+    uint32_t* pre = reinterpret_cast<uint32_t*>(nrm + kHaloRows * 2 * kMaxWidths);  // [kHaloRows][pw]
+    __shared__ int32_t cnt[kSpsRows];
+
+    const int64_t tt0 = t_begin + static_cast<int64_t>(blockIdx.x) * kSpsTile;
+    const int64_t tile_end = min(tt0 + kSpsTile, t_end);
+    const int d0 = blockIdx.y * kSpsRows;
+    const int j = static_cast<int>((tt0 - t_begin) / B);
+    const int64_t lo = max(tt0 - 1, static_cast<int64_t>(0));
+    const int64_t hi = (t_total < 0 || tile_end < t_total) ? tile_end + 1 : tile_end;  // best valid in [lo, hi)
+    const int tid = threadIdx.x;
+
+    if (tid < kSpsRows) cnt[tid] = 0;
+    for (int i = tid; i < kHaloRows * 2 * sc.nw; i += 256) {
+        const int r = i / (2 * sc.nw), k = i - r * (2 * sc.nw);
+        const int d = d0 - 1 + r;
+        nrm[r * 2 * kMaxWidths + k] = (d >= 0 && d < ndm) ? norms[(static_cast<int64_t>(j) * ndm + d) * (2 * sc.nw) + k] : 0.0;
+    }
+    // D columns into pre[r][1 + i], i = column t_tile0 - 1 + i
+    for (int i = tid; i < kHaloRows * tw; i += 256) {
+        const int r = i / tw, c = i - r * tw;
+        const int d = d0 - 1 + r;
+        const int64_t col = tt0 - 1 + c - dd_t0;
+        uint32_t v = 0;
+        if (d >= 0 && d < ndm && col >= 0 && col < dd_n) v = static_cast<uint32_t>(dd[static_cast<int64_t>(d) * dd_pitch + col]);
+        pre[r * pw + 1 + c] = v;
+    }
+    if (tid < kHaloRows) pre[tid * pw] = 0;
+    __syncthreads();
+    // inclusive prefix per row, one wave per row, modulo 2^32 (exact window sums < 2^32)
+    {
+        const int wave = tid >> 6, lane = tid & 63;
+        const int per = (pw + 63) / 64;
+        for (int r = wave; r < kHaloRows; r += 4) {
+            uint32_t* pr = pre + r * pw;
+            const int a = lane * per, b = min(a + per, pw);
+            uint32_t s = 0;
+            for (int i = a; i < b; ++i) s += pr[i];
+            uint32_t incl = s;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t u = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += u;
+            }
+            uint32_t run = incl - s;
+            for (int i = a; i < b; ++i) {
+                run += pr[i];
+                pr[i] = run;
+            }
+        }
+    }
+    __syncthreads();
+    // best S/N over widths for every halo cell
+    for (int i = tid; i < kHaloRows * kHaloCols; i += 256) {
+        const int r = i / kHaloCols, c = i - r * kHaloCols;
+        const int d = d0 - 1 + r;
+        const int64_t t = tt0 - 1 + c;
+        double v = -__builtin_huge_val();
+        if (d >= 0 && d < ndm && t >= lo && t < hi) {
+            const uint32_t* pr = pre + r * pw + c;      // pr[k] = sum of columns c..c+k-1
+            const double* nr = nrm + r * 2 * kMaxWidths;
+            for (int k = 0; k < sc.nw; ++k) {
+                const uint32_t s = pr[sc.widths[k]] - pr[0];
+                const double snr = (static_cast<double>(s) - nr[k]) * nr[sc.nw + k];
+                if (k == 0 || snr > v) v = snr;
+            }
+        }
+        best[i] = v;
+    }
+    __syncthreads();
+    // 3x3 peak test for the inner rows, 64 consecutive starts per wave step
+    for (int item = tid; item < kSpsRows * kSpsTile; item += 256) {
+        const int ri = item / kSpsTile, tc = item - ri * kSpsTile;
+        const int d = d0 + ri;
+        const int64_t t = tt0 + tc;
+        bool ok = false;
+        if (d < ndm && t < tile_end) {
+            const double* m = best + (ri + 1) * kHaloCols + (tc + 1);
+            const double v = m[0];
+            ok = v >= threshold && v > m[-kHaloCols - 1] && v > m[-kHaloCols] && v > m[-kHaloCols + 1] &&
+                 v > m[-1] && v >= m[1] && v >= m[kHaloCols - 1] && v >= m[kHaloCols] && v >= m[kHaloCols + 1];
+            if (best_out) best_out[static_cast<int64_t>(d) * best_pitch + (t - t_begin)] = static_cast<float>(v);
+        }
+        const uint64_t bal = __ballot(ok);
+        if ((tid & 63) == 0 && d < ndm) {
+            const int64_t w = (tt0 - t_begin) / 32 + tc / 32;
+            *reinterpret_cast<uint64_t*>(mask + static_cast<int64_t>(d) * nwords + w) = bal;
+            if (bal) atomicAdd(&cnt[ri], __popcll(bal));
+        }
+    }
+    __syncthreads();
+    if (tid < kSpsRows && d0 + tid < ndm && cnt[tid] > 0) atomicAdd(&rowcount[d0 + tid], cnt[tid]);
+}
+
+// ---- emission -------------------------------------------------------------------
+__device__ int block_excl_scan(int v, int* total, int* sh) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += u;
+    }
+    if (lane == 63) sh[wave] = incl;
+    __syncthreads();
+    int base = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        if (w < wave) base += sh[w];
+        tot += sh[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return base + incl - v;
+}
+
+__global__ __launch_bounds__(256) void sps_emit_kernel(
+    const int32_t* __restrict__ dd, int64_t dd_pitch, int64_t dd_t0, int64_t t_begin, int32_t B,
+    int32_t ndm, SpsConst sc, const double* __restrict__ norms, const int32_t* __restrict__ rowcount,
+    const uint32_t* __restrict__ mask, int64_t nwords, aa_candidate_t* __restrict__ cand, int32_t cap,
+    int32_t* __restrict__ count) {
+    __shared__ int sh[4];
+    __shared__ int64_t red[4];
+    const int d = blockIdx.x;
+    int64_t off = 0;
+    for (int i = threadIdx.x; i < d; i += 256) off += rowcount[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) off += __shfl_xor(off, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = off;
+    __syncthreads();
+    off = red[0] + red[1] + red[2] + red[3];
+    const int mine = rowcount[d];
+    if (d == ndm - 1 && threadIdx.x == 0) *count = static_cast<int32_t>(min<int64_t>(off + mine, 0x7fffffff));
+    if (mine == 0 || off >= cap) return;
+    const int32_t* row = dd + static_cast<int64_t>(d) * dd_pitch - dd_t0;
+    int64_t running = off;
+    for (int64_t k0 = 0; k0 < nwords; k0 += 256) {
+        const int64_t k = k0 + threadIdx.x;
+        uint32_t word = k < nwords ? mask[static_cast<int64_t>(d) * nwords + k] : 0u;
+        int total;
+        const int excl = block_excl_scan(__popc(word), &total, sh);
+        int64_t pos = running + excl;
+        while (word) {
+            const int b = __ffs(word) - 1;
+            word &= word - 1;
+            if (pos < cap) {
+                const int64_t t = t_begin + 32 * k + b;
+                const int jb = static_cast<int>((t - t_begin) / B);
+                const double* nr = norms + (static_cast<int64_t>(jb) * ndm + d) * (2 * sc.nw);
+                uint32_t s = 0;
+                int i = 0;
+                double v = 0.0;
+                int wbest = sc.widths[0];
+                for (int q = 0; q < sc.nw; ++q) {
+                    for (; i < sc.widths[q]; ++i) s += static_cast<uint32_t>(row[t + i]);
+                    const double snr = (static_cast<double>(s) - nr[q]) * nr[sc.nw + q];
+                    if (q == 0 || snr > v) {
+                        v = snr;
+                        wbest = sc.widths[q];
+                    }
+                }
+                aa_candidate_t c;
+                c.dm_idx = d;
+                c.width = wbest;
+                c.t = t;
+                c.snr = static_cast<float>(v);
+                c.beam = 0;
+                cand[pos] = c;
+            }
+            ++pos;
+        }
+        running += total;
+        if (running >= cap) break;
+    }
+}
+
+size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+struct WorkLayout {
+    size_t norms, rowcount, mask, total;
+    int64_t nblk, ntiles, nwords;
+};
+
+WorkLayout layout(const aa_plan_s* p, int64_t n_starts) {
+    WorkLayout L{};
+    L.nblk = (n_starts + p->stat_block - 1) / p->stat_block;
+    L.ntiles = (n_starts + kSpsTile - 1) / kSpsTile;
+    L.nwords = L.ntiles * (kSpsTile / 32);
+    L.norms = 0;
+    L.rowcount = align256(static_cast<size_t>(L.nblk) * p->ndm * 2 * p->nwidths * sizeof(double));
+    L.mask = L.rowcount + align256(static_cast<size_t>(p->ndm) * sizeof(int32_t));
+    L.total = L.mask + align256(static_cast<size_t>(p->ndm) * L.nwords * sizeof(uint32_t));
+    return L;
+}
+
+}  // namespace
+
+size_t sps_work_bytes(const aa_plan_s* p, int64_t n_starts) { return n_starts > 0 ? layout(p, n_starts).total : 0; }
+
+int launch_single_pulse(const aa_plan_s* p, const int32_t* d_dd, int64_t dd_pitch, int64_t dd_t0, int64_t dd_n,
+                        int64_t t_begin, int64_t t_end, int64_t t_total, void* d_work, aa_candidate_t* d_cand,
+                        int32_t cap, int32_t* d_count, float* d_best, int64_t best_pitch, hipStream_t stream) {
+    const int64_t n = t_end - t_begin;
+    const WorkLayout L = layout(p, n);
+    uint8_t* w = static_cast<uint8_t*>(d_work);
+    double* norms = reinterpret_cast<double*>(w + L.norms);
+    int32_t* rowcount = reinterpret_cast<int32_t*>(w + L.rowcount);
+    uint32_t* mask = reinterpret_cast<uint32_t*>(w + L.mask);
+    SpsConst sc{};
+    sc.nw = p->nwidths;
+    sc.wmax = p->wmax;
+    for (int k = 0; k < p->nwidths; ++k) {
+        sc.widths[k] = p->widths[k];
+        sc.sqrtw[k] = p->sqrtw[k];
+    }
+    hipLaunchKernelGGL(sps_stats_kernel, dim3(static_cast<unsigned>(L.nblk), static_cast<unsigned>(p->ndm)), dim3(256),
+                       0, stream, d_dd, dd_pitch, dd_t0, t_begin, t_end, p->stat_block, p->ndm, sc, norms, rowcount);
+    AA_HIP(hipGetLastError());
+    const int tw = kSpsTile + 1 + p->wmax;
+    const size_t lds = sizeof(double) * (kHaloRows * kHaloCols + kHaloRows * 2 * kMaxWidths) +
+                       sizeof(uint32_t) * kHaloRows * (tw + 1);
+    const unsigned rowblocks = static_cast<unsigned>((p->ndm + kSpsRows - 1) / kSpsRows);
+    hipLaunchKernelGGL(sps_detect_kernel, dim3(static_cast<unsigned>(L.ntiles), rowblocks), dim3(256), lds, stream,
+                       d_dd, dd_pitch, dd_t0, dd_n, t_begin, t_end, t_total, p->stat_block, p->ndm,
+                       static_cast<double>(p->threshold), sc, norms, rowcount, mask, L.nwords, d_best, best_pitch);
+    AA_HIP(hipGetLastError());
+    hipLaunchKernelGGL(sps_emit_kernel, dim3(static_cast<unsigned>(p->ndm)), dim3(256), 0, stream, d_dd, dd_pitch,
+                       dd_t0, t_begin, p->stat_block, p->ndm, sc, norms, rowcount, mask, L.nwords, d_cand, cap,
+                       d_count);
+    AA_HIP(hipGetLastError());
+    return AA_OK;
+}
+
+}  // namespace aa
+
+extern "C" int aa_single_pulse_work_bytes(aa_plan_t p, int64_t n_starts, size_t* out) {
+    using namespace aa;
+    if (!p || !out || n_starts < 1) return fail(AA_EINVAL, "aa_single_pulse_work_bytes: bad argument");
+    *out = sps_work_bytes(p, n_starts);
+    return AA_OK;
+}
+
+extern "C" int aa_single_pulse(aa_plan_t p, const int32_t* d_dd, int64_t dd_pitch, int64_t dd_t0, int64_t dd_n,
+                               int64_t t_begin, int64_t t_end, int64_t t_total, void* d_work, size_t work_bytes,
+                               aa_candidate_t* d_cand, int32_t cap, int32_t* d_count, float* d_best,
+                               int64_t best_pitch, void* stream) {
+    using namespace aa;
+    if (!p || !d_dd || !d_work || !d_count || (cap > 0 && !d_cand))
+        return fail(AA_EINVAL, "aa_single_pulse: null argument");
+    if (p->device < 0) return fail(AA_EINVAL, "aa_single_pulse: plan was created host-only");
+    if (p->nwidths > kMaxWidths) return fail(AA_EINVAL, "aa_single_pulse: more than 32 widths");
+    if (cap < 0) return fail(AA_EINVAL, "aa_single_pulse: cap < 0");
+    if (t_begin < 0 || t_end <= t_begin || t_begin % p->stat_block)
+        return fail(AA_EINVAL, "aa_single_pulse: need 0 <= t_begin < t_end and t_begin a multiple of stat_block");
+    if (t_total >= 0 && t_end > t_total) return fail(AA_EINVAL, "aa_single_pulse: t_end > t_total");
+    if (dd_n < 1 || dd_n > dd_pitch) return fail(AA_EINVAL, "aa_single_pulse: need 1 <= dd_n <= dd_pitch");
+    if (dd_t0 > (t_begin > 0 ? t_begin - 1 : t_begin)) return fail(AA_EINVAL, "aa_single_pulse: plane misses the left halo column");
+    const int64_t right = (t_total >= 0 && t_end >= t_total) ? t_end : t_end + 1;
+    if (dd_t0 + dd_n < right + p->wmax - 1) return fail(AA_EINVAL, "aa_single_pulse: plane too short for the right edge");
+    if (work_bytes < sps_work_bytes(p, t_end - t_begin)) return fail(AA_EINVAL, "aa_single_pulse: work buffer too small");
+    if (d_best && best_pitch < t_end - t_begin) return fail(AA_EINVAL, "aa_single_pulse: best_pitch too small");
+    if (reinterpret_cast<uintptr_t>(d_work) & 255) return fail(AA_EINVAL, "aa_single_pulse: d_work must be 256-byte aligned");
+    return launch_single_pulse(p, d_dd, dd_pitch, dd_t0, dd_n, t_begin, t_end, t_total, d_work, d_cand, cap, d_count,
+                               d_best, best_pitch, static_cast<hipStream_t>(stream));
+}

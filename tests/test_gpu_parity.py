@@ -1,0 +1,160 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, element by element.
+
+Dedispersion must be bit-exact. Candidate lists must be identical, with S/N within
+1e-5 relative. Both sides evaluate the same float64 formulas with the same rounding
+points, so the S/N values are expected to agree exactly.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import dm_plan
+from synth.filterbank import Pulse, make_filterbank
+from tests.gpu_util import assert_candidates_equal, run_gpu, say, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+def _plan(nchan, nsamp, f_top, foff, tsamp, dms, widths, thr, stat_block=0):
+    from paper_2101_00941_amd import Plan
+    return Plan(nchan, nsamp, f_top, foff, tsamp, dms, widths, thr, stat_block)
+
+
+def test_tiny_workload_dedisp_and_candidates(tiny, tiny_oracle):
+    w, x = tiny
+    say("tiny_128ch_32k: 128 ch x 32768, 100 DMs")
+    from paper_2101_00941_amd import Plan
+    p = Plan.from_workload(w)
+    assert np.array_equal(p.shifts().astype(np.int64), tiny_oracle["shifts"])
+    r = run_gpu(p, x, w["nsamp"])
+    assert np.array_equal(r["D"], tiny_oracle["D"])
+    assert_candidates_equal(r["candidates"], tiny_oracle["candidates"])
+    assert r["count"] == len(tiny_oracle["candidates"])
+    assert np.array_equal(r["best"], tiny_oracle["best"])
+    top = max(r["candidates"], key=lambda c: c[3])
+    assert top[0] == 50
+
+
+DEDISP_CASES = [
+    # nchan, nsamp, f_top, foff, tsamp, dms
+    (1, 3000, 1400.0, 1.0, 64e-6, [0.0, 10.0, 100.0]),
+    (7, 5003, 1500.0, 3.0, 64e-6, list(np.linspace(0, 50, 5))),
+    (33, 4099, 1500.0, 1.0, 64e-6, list(np.arange(17) * 3.0)),
+    (16, 1300, 1500.0, 2.0, 64e-6, list(np.arange(16) * 0.5)),            # n_out < one time tile
+    (300, 10000, 1450.0, 300.0 / 300, 64e-6, list(np.arange(40) * 2.0)),
+    (64, 70001, 1450.0, 300.0 / 64, 64e-6, list(dm_plan(700)[::10])),      # doubling-step plan
+    (48, 60000, 1200.0, 4.0, 64e-6, list(np.arange(9) * 60.0)),            # wide DM steps: small blocks
+    (257, 8000, 1500.0, 0.5, 64e-6, list(np.arange(21) * 1.0)),            # flush after 256 channels
+]
+
+
+@pytest.mark.parametrize("case", range(len(DEDISP_CASES)))
+def test_dedisp_shapes_bit_exact(case):
+    nchan, nsamp, f_top, foff, tsamp, dms = DEDISP_CASES[case]
+    say(f"dedisp case {case}: nchan {nchan} nsamp {nsamp} ndm {len(dms)}")
+    rng = np.random.default_rng(case)
+    x = rng.integers(0, 256, (nchan, nsamp), dtype=np.uint8)
+    p = _plan(nchan, nsamp, f_top, foff, tsamp, dms, [1, 2], 1e9)
+    s = p.shifts().astype(np.int64)
+    want = oracle.dedisperse(x, s, nsamp)
+    for pitch in (None, (nsamp + 255) // 256 * 256 + 512):
+        xd = to_device(x, nsamp, pitch)
+        D = p.dedisperse(xd, n_in=nsamp)
+        got = D[:, :want.shape[1]].cpu().numpy().astype(np.int64)
+        assert np.array_equal(got, want), (case, pitch)
+
+
+def test_dedisp_saturated_input_exact():
+    # every sample 255: the int32 sums reach nchan * 255
+    nchan, nsamp = 1024, 5000
+    x = np.full((nchan, nsamp), 255, np.uint8)
+    p = _plan(nchan, nsamp, 1500.0, 0.25, 64e-6, list(np.arange(20) * 2.0), [1], 1e9)
+    D = p.dedisperse(to_device(x, nsamp), n_in=nsamp)
+    assert (D[:, :nsamp - p.info["maxshift"]].cpu().numpy() == nchan * 255).all()
+
+
+def _signal(nchan=32, nsamp=40000, seed=8):
+    pulses = [Pulse(30.0, 8191.0, 4.0, 90.0), Pulse(12.0, 16384.0, 2.0, 90.0), Pulse(55.0, 31000.0, 8.0, 70.0),
+              Pulse(5.0, 4095.0, 1.0, 120.0)]
+    return make_filterbank(nchan, nsamp, 1500.0, 1.5, 64e-6, pulses, seed=seed)
+
+
+@pytest.mark.parametrize("widths", [[1, 2, 4, 8, 16], [1, 3, 10, 50], [7]])
+def test_multiblock_candidates(widths):
+    nchan, nsamp = 32, 40000
+    x = _signal(nchan, nsamp)
+    dms = np.arange(0, 60, 1.0)
+    say(f"multiblock widths {widths}")
+    want = oracle.run(x, nsamp, 1500.0, 1.5, 64e-6, dms, widths, 5.0, stat_block=4096, want_best=True)
+    p = _plan(nchan, nsamp, 1500.0, 1.5, 64e-6, dms, widths, 5.0, 4096)
+    r = run_gpu(p, x, nsamp)
+    assert np.array_equal(r["D"], want["D"])
+    assert len(want["candidates"]) > 3
+    assert_candidates_equal(r["candidates"], want["candidates"])
+    assert np.array_equal(r["best"], want["best"])
+
+
+def test_subrange_call_matches_oracle():
+    # one chunk in the middle of the signal: t_begin > 0, right neighbour column present
+    import torch
+    from paper_2101_00941_amd import candidates_as_tuples, candidates_to_numpy
+    nchan, nsamp = 32, 40000
+    x = _signal(nchan, nsamp)
+    dms = np.arange(0, 60, 1.0)
+    widths = [1, 2, 4, 8, 16]
+    p = _plan(nchan, nsamp, 1500.0, 1.5, 64e-6, dms, widths, 5.0, 4096)
+    s = p.shifts().astype(np.int64)
+    m = int(s.max())
+    a, b = 8192, 20480
+    lo, hi = a - 1, b + 16 + m
+    xs = np.ascontiguousarray(x[:, lo:hi])
+    Dw = oracle.dedisperse(xs, s, hi - lo, m)
+    want, _ = oracle.single_pulse(Dw, lo, a, b, -1, widths, 5.0, 4096)
+    D = p.dedisperse(to_device(xs, hi - lo), n_in=hi - lo)
+    cand, count, _ = p.single_pulse(D, dd_t0=lo, dd_n=hi - lo - m, t_begin=a, t_end=b, t_total=-1, cap=4096)
+    torch.cuda.synchronize()
+    got = candidates_as_tuples(candidates_to_numpy(cand, count))
+    assert_candidates_equal(got, want)
+    assert len(want) > 0
+
+
+def test_candidate_capacity_overflow():
+    import torch
+    from paper_2101_00941_amd import candidates_as_tuples, candidates_to_numpy
+    nchan, nsamp = 32, 40000
+    x = _signal(nchan, nsamp)
+    dms = np.arange(0, 60, 1.0)
+    want = oracle.run(x, nsamp, 1500.0, 1.5, 64e-6, dms, [1, 2, 4], 4.0, stat_block=4096)["candidates"]
+    p = _plan(nchan, nsamp, 1500.0, 1.5, 64e-6, dms, [1, 2, 4], 4.0, 4096)
+    D = p.dedisperse(to_device(x, nsamp), n_in=nsamp)
+    cand, count, _ = p.single_pulse(D, cap=5)
+    torch.cuda.synchronize()
+    assert int(count.item()) == len(want) > 5
+    got = candidates_as_tuples(candidates_to_numpy(cand, count, cap=5))
+    assert_candidates_equal(got, want[:5])
+
+
+def test_constant_input_no_candidates():
+    import torch
+    nchan, nsamp = 16, 9000
+    x = np.full((nchan, nsamp), 100, np.uint8)
+    p = _plan(nchan, nsamp, 1500.0, 1.0, 64e-6, [0.0, 1.0, 2.0], [1, 2], 0.5, 1024)
+    D = p.dedisperse(to_device(x, nsamp), n_in=nsamp)
+    cand, count, best = p.single_pulse(D, cap=16, want_best=True)
+    torch.cuda.synchronize()
+    assert int(count.item()) == 0
+    assert (best[:, :p.info["n_start"]].cpu().numpy() == 0).all()
+
+
+def test_single_pulse_argument_errors():
+    import torch
+    from paper_2101_00941_amd import AAError
+    p = _plan(16, 9000, 1500.0, 1.0, 64e-6, [0.0, 1.0], [1, 2], 6.0, 1024)
+    D = torch.zeros((2, 9000), dtype=torch.int32, device="cuda")
+    with pytest.raises(AAError):
+        p.single_pulse(D, t_begin=100, t_end=2000)           # not a stat-block multiple
+    with pytest.raises(AAError):
+        p.single_pulse(D, dd_t0=1024, dd_n=4000, t_begin=1024, t_end=2048, t_total=-1)  # no left halo
+    with pytest.raises(AAError):
+        p.single_pulse(D, dd_n=2000, t_begin=0, t_end=2048, t_total=-1)  # no right edge columns
