@@ -115,6 +115,37 @@ void aa_plan_destroy(aa_plan_t plan);
 int aa_dedisperse(aa_plan_t plan, const uint8_t* d_in, int64_t in_pitch, int64_t n_in,
                   int32_t* d_out, int64_t out_pitch, void* stream);
 
+/* ---- dedispersion kernel variants and autotuner -----------------------------
+ * aa_dedisperse has several kernel variants. They differ in work-group shape:
+ * waves per work-group, trials per wave (so trials per DM block), LDS budget, and
+ * the lane-to-sample layout.
+ * All variants compute the same bit-exact result. Preparing a variant builds its
+ * tables on the host and uploads them once. That is plan-time work, like aa_plan,
+ * and must not run concurrently with compute calls on the same plan.
+ *   aa_variant_count()            number of variants
+ *   aa_variant_info(v, out)       shape of variant v
+ *   aa_plan_set_variant(plan, v)  prepare v and use it for aa_dedisperse
+ *   aa_plan_get_variant(plan, v)  variant in use
+ *   aa_autotune(...)              time every variant on the caller's buffers (reps runs
+ *                                 each, HIP events on `stream`), select the fastest,
+ *                                 and write the per-variant mean ms to ms_out
+ *                                 [aa_variant_count()]. If AA_TUNE_CACHE names a file,
+ *                                 the choice is read from and written to that JSON
+ *                                 cache, keyed by device arch and plan shape.
+ * d_out receives the dedispersed plane of the last run.
+ */
+typedef struct {
+    int32_t id, waves, dm_per_wave, trials_per_block, lds_bytes;
+    int32_t layout;   /* 0: a lane owns 16 contiguous samples; 1: four groups of 4, 256 apart */
+} aa_variant_t;
+
+int aa_variant_count(void);
+int aa_variant_info(int32_t v, aa_variant_t* out);
+int aa_plan_set_variant(aa_plan_t plan, int32_t v);
+int aa_plan_get_variant(aa_plan_t plan, int32_t* v);
+int aa_autotune(aa_plan_t plan, const uint8_t* d_in, int64_t in_pitch, int64_t n_in, int32_t* d_out,
+                int64_t out_pitch, int32_t reps, void* stream, float* ms_out);
+
 /* ---- single-pulse search (A3-A5) -------------------------------------------
  * Section 2.2 (single-pulse search phase). Input: a dedispersed plane whose column
  * j holds absolute start dd_t0 + j, valid for j < dd_n. Output: the candidates

@@ -36,6 +36,11 @@ class PlanInfo(C.Structure):
                 ("out_pitch", C.c_int64), ("work_bytes", C.c_size_t), ("device", C.c_int32)]
 
 
+class VariantInfo(C.Structure):
+    _fields_ = [("id", C.c_int32), ("waves", C.c_int32), ("dm_per_wave", C.c_int32),
+                ("trials_per_block", C.c_int32), ("lds_bytes", C.c_int32), ("layout", C.c_int32)]
+
+
 class AAError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
@@ -67,6 +72,11 @@ def lib():
         "aa_plan_destroy": (None, [vp]),
         "aa_dedisperse": (C.c_int, [vp, vp, i64, i64, vp, i64, vp]),
         "aa_single_pulse_work_bytes": (C.c_int, [vp, i64, C.POINTER(sz)]),
+        "aa_variant_count": (C.c_int, []),
+        "aa_variant_info": (C.c_int, [i32, C.POINTER(VariantInfo)]),
+        "aa_plan_set_variant": (C.c_int, [vp, i32]),
+        "aa_plan_get_variant": (C.c_int, [vp, C.POINTER(i32)]),
+        "aa_autotune": (C.c_int, [vp, vp, i64, i64, vp, i64, i32, vp, C.POINTER(C.c_float)]),
         "aa_single_pulse": (C.c_int, [vp, vp, i64, i64, i64, i64, i64, i64, vp, sz, vp, i32, vp, vp, i64, vp]),
     }
     for name, (res, args) in sig.items():

@@ -107,6 +107,38 @@ class Plan:
                                       _stream_handle(stream)))
         return out
 
+    @staticmethod
+    def variants():
+        L = N.lib()
+        out = []
+        for v in range(L.aa_variant_count()):
+            vi = N.VariantInfo()
+            N.check(L.aa_variant_info(v, C.byref(vi)))
+            out.append({k: getattr(vi, k) for k, _ in N.VariantInfo._fields_})
+        return out
+
+    @property
+    def variant(self):
+        v = C.c_int32()
+        N.check(N.lib().aa_plan_get_variant(self._h, C.byref(v)))
+        return v.value
+
+    def set_variant(self, v):
+        N.check(N.lib().aa_plan_set_variant(self._h, int(v)))
+
+    def autotune(self, x, n_in=None, out=None, reps=2, stream=None):
+        """aa_autotune on the caller's buffers. Returns the per-variant mean ms (-1: from cache)."""
+        import torch
+        n_in = x.shape[1] if n_in is None else int(n_in)
+        n_out = n_in - self.info["maxshift"]
+        if out is None:
+            out = torch.empty((self.info["ndm"], (n_out + 63) // 64 * 64), dtype=torch.int32, device=x.device)
+        nv = N.lib().aa_variant_count()
+        ms = (C.c_float * nv)()
+        N.check(N.lib().aa_autotune(self._h, _ptr(x), x.stride(0), n_in, _ptr(out), out.stride(0), int(reps),
+                                    _stream_handle(stream), ms))
+        return [float(v) for v in ms]
+
     def work_bytes(self, n_starts):
         v = C.c_size_t()
         N.check(N.lib().aa_single_pulse_work_bytes(self._h, int(n_starts), C.byref(v)))

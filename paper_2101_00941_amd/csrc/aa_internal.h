@@ -22,17 +22,24 @@ int hip_fail(hipError_t e, const char* what);
         if (aa_e_ != hipSuccess) return ::aa::hip_fail(aa_e_, #call); \
     } while (0)
 
-// Dedispersion tiling (compile-time shape of the kernel). A work-group of
-// kDedispWaves waves covers one DM block (up to kDedispWaves * kDmPerWave trials)
-// and one time tile of 64 * kSampPerLane samples. Each channel pass stages
-// kChanPerPass input rows in LDS.
+// Dedispersion tiling. A work-group of `waves` waves owns one DM block of up to
+// waves * dpw consecutive trials and one time tile of 1024 samples (16 per lane).
+// Each wave owns dpw trials. A channel pass stages `cp` input rows of `row` bytes
+// in LDS, double-buffered.
 constexpr int kSampPerLane = 16;
-constexpr int kDmPerWave = 4;
-constexpr int kDedispWaves = 4;
-constexpr int kChanPerPass = 16;
 constexpr int kTimeTile = 64 * kSampPerLane;
-constexpr int kDmBlock = kDedispWaves * kDmPerWave;
-constexpr int kMaxRowBytes = 1664;   // LDS row length limit for one staged channel row
+constexpr int kChanPerPass = 16;
+
+struct DedispVariant {
+    int id;          // index into the kernel table (dedisp.hip)
+    int waves;       // waves per work-group
+    int dpw;         // DM trials per wave
+    int lds_bytes;   // LDS budget per work-group (both buffers)
+    int layout;      // 0: lane owns 16 contiguous samples (ds_read_b128); 1: four 4-sample groups (ds_read2_b32)
+};
+constexpr int kNumDedispVariants = 6;
+extern const DedispVariant kDedispVariants[kNumDedispVariants];
+constexpr int kDefaultDedispVariant = 0;
 
 // Single-pulse-search tiling: a work-group covers kSpsRows DM rows and kSpsTile starts.
 constexpr int kSpsTile = 256;
@@ -40,9 +47,24 @@ constexpr int kSpsRows = 8;
 
 struct DmBlock {
     int32_t first;   // first DM trial of the block
-    int32_t count;   // trials in the block (<= kDmBlock)
+    int32_t count;   // trials in the block (<= waves * dpw)
     int32_t row;     // LDS row length (bytes) the block needs, multiple of 16
     int32_t pad;
+};
+
+// Per-variant tables. For block b and channel c:
+//   base[b][c]       = s[first][c] & ~15   (16-byte-aligned start of the staged row)
+//   offs[b][c][i]    = s[first+i][c] - base[b][c], for i < waves*dpw (0 for absent trials)
+// Channels are padded to a multiple of kChanPerPass. Padded rows are zero.
+struct DedispTables {
+    int variant = -1;
+    int bd = 0;                      // trials per block
+    int nchan_pad = 0;
+    int32_t max_row = 0;
+    std::vector<DmBlock> blocks;
+    DmBlock* d_blocks = nullptr;
+    int32_t* d_base = nullptr;
+    int32_t* d_offs = nullptr;
 };
 
 }  // namespace aa
@@ -57,21 +79,21 @@ struct aa_plan_s {
     std::vector<int32_t> widths;
     std::vector<double> sqrtw;            // sqrt(double(w)), rounded once on the host
     std::vector<int32_t> shifts;          // [ndm][nchan]
-    // dedispersion tiling tables
-    std::vector<aa::DmBlock> blocks;
-    std::vector<int32_t> offs;            // [ndm][nchan]: s[d][c] - (s[first][c] & ~15)
-    int32_t max_row = 0;
+    // dedispersion tiling tables, one set per kernel variant that has been prepared
+    aa::DedispTables tables[aa::kNumDedispVariants];
+    int variant = aa::kDefaultDedispVariant;   // variant used by aa_dedisperse
     // device copies (uploaded once at plan time)
     int device = -1;
     int32_t* d_shifts = nullptr;
-    int32_t* d_offs = nullptr;
-    aa::DmBlock* d_blocks = nullptr;
     int32_t* d_widths = nullptr;
 };
 
 namespace aa {
+// Builds (host) and uploads (device, unless the plan is host-only) the tables of a variant.
+int prepare_variant(aa_plan_s* p, int variant);
+void free_tables(DedispTables& t);
 // Launchers (dedisp.hip, sps.hip). Arguments are validated by the callers.
-int launch_dedisperse(const aa_plan_s* p, const uint8_t* d_in, int64_t in_pitch, int64_t n_in,
+int launch_dedisperse(const aa_plan_s* p, int variant, const uint8_t* d_in, int64_t in_pitch, int64_t n_in,
                       int32_t* d_out, int64_t out_pitch, hipStream_t stream);
 size_t sps_work_bytes(const aa_plan_s* p, int64_t n_starts);
 int launch_single_pulse(const aa_plan_s* p, const int32_t* d_dd, int64_t dd_pitch, int64_t dd_t0,

@@ -2,26 +2,30 @@
 // section 2.1):  D[d][t] = sum_c X[c][t + s[d][c]], exact in integers.
 //
 // Shape of the kernel:
-//  * A work-group of 4 waves owns one DM block (up to 16 consecutive trials) and one
-//    time tile of 1024 samples. Each wave owns 4 trials. Each lane owns 16
-//    consecutive samples of each of its trials.
-//  * The input is consumed in channel passes. A pass stages 16 channel rows in LDS
-//    with coalesced 16-byte global loads. A row holds the bytes
-//    [t0 + (s[first][c] & ~15), + row), which covers every trial of the block. Each
-//    staged byte is then reused by all trials of the block.
-//  * The inner step for one (channel, trial): two aligned ds_read_b128 give the 32
-//    bytes around the lane's 16-sample window. Eight v_perm_b32 extract the window
-//    as zero-extended 16-bit pairs. The byte offset (o & 3) picks the selector, and
-//    (o >> 2) & 3 picks the registers through a uniform branch. The pairs are then
-//    added into packed u16x2 accumulators. A u16 half holds up to 257 * 255, so the
-//    pairs are widened into int32 accumulators every 256 channels.
-//  * MFMA is not used: this is shift-and-add, not a dense contraction.
+//  * A work-group of W waves owns one DM block of up to W * DPW consecutive trials
+//    and one time tile of 1024 samples. Each wave owns DPW trials. Each lane owns
+//    16 consecutive samples of each of its trials.
+//  * The input is consumed in passes of 16 channel rows. A pass is staged in LDS
+//    with direct global->LDS 16-byte loads (global_load_lds_dwordx4), with no
+//    register round trip, into one of two buffers. The next pass streams in while
+//    the current one is summed. A staged row holds the bytes
+//    [t0 + (s[first][c] & ~15), + row), which cover every trial of the block. So
+//    each staged byte is reused by all trials of the block.
+//  * The inner step for one (channel, trial): two aligned ds_read_b128 bring in
+//    the 32 bytes around the lane's 16-sample window. Eight v_perm_b32 extract the
+//    window as zero-extended 16-bit pairs. The byte phase (o & 3) picks the
+//    selector, and (o >> 2) & 3 picks the registers through a uniform branch. Two
+//    channels are folded per v_add3_u32 into packed u16x2 accumulators. A 16-bit
+//    half holds up to 257 * 255, so the pairs are widened into int32 accumulators
+//    every 256 channels.
+//  * No MFMA: this is shift-and-add, not a dense contraction.
 #include "aa_internal.h"
 
 namespace aa {
 namespace {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) void lds_void;
 
 // Work-group i runs on XCD i % 8. Give each XCD a contiguous run of logical tiles
 // (adjacent DM blocks of the same time tile), so that their overlapping input rows
@@ -33,8 +37,9 @@ __device__ __forceinline__ int xcd_remap(int bid, int n) {
 }
 
 template <int Q>
-__device__ __forceinline__ void extract16(const uint32_t (&w)[8], uint32_t sel0, uint32_t sel1,
+__device__ __forceinline__ void extract16(const u32x4& x0, const u32x4& x1, uint32_t sel0, uint32_t sel1,
                                           uint32_t (&p)[8]) {
+    const uint32_t w[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const int i = Q + (j >> 1);
@@ -42,54 +47,101 @@ __device__ __forceinline__ void extract16(const uint32_t (&w)[8], uint32_t sel0,
     }
 }
 
-template <int KS, int DPW, int WAVES, int CP>
-__global__ __launch_bounds__(64 * WAVES) void dedisp_kernel(
-    const uint8_t* __restrict__ in, int64_t in_pitch, const int32_t* __restrict__ shifts,
-    const int32_t* __restrict__ offs, const DmBlock* __restrict__ blocks, int nblk, int nchan,
+// The 16 samples of a lane's window, as 8 zero-extended u16 pairs (sample 2j in the
+// low half, 2j+1 in the high half). x0 and x1 are the two aligned 16-byte reads at
+// the lane's slot + (o & ~15), where o is the trial's byte offset within the row.
+__device__ __forceinline__ void window16(const u32x4& x0, const u32x4& x1, int o, uint32_t (&p)[8]) {
+    const uint32_t r = static_cast<uint32_t>(o & 3);
+    const uint32_t sel0 = 0x0C000C00u | ((r + 1u) << 16) | r;
+    const uint32_t sel1 = sel0 + 0x00020002u;
+    switch ((o >> 2) & 3) {
+        case 0: extract16<0>(x0, x1, sel0, sel1, p); break;
+        case 1: extract16<1>(x0, x1, sel0, sel1, p); break;
+        case 2: extract16<2>(x0, x1, sel0, sel1, p); break;
+        default: extract16<3>(x0, x1, sel0, sel1, p); break;
+    }
+}
+
+// Interleaved layout: lane l owns the four 4-sample groups t0 + 256 m + 4 l + [0, 4),
+// m = 0..3. A group's window starts at byte o + 256 m + 4 l of the row. Two dwords at
+// the 4-byte-aligned address below it (one ds_read2_b32) hold all 4 bytes, for any
+// phase r = o & 3. So the perm selector depends only on r, and there is no
+// register selection: this path is branch-free. Consecutive lanes read consecutive
+// dwords, so there are no bank conflicts.
+__device__ __forceinline__ void window4x4(const uint8_t* lanep, int o, uint32_t (&p)[8]) {
+    const uint32_t* w = reinterpret_cast<const uint32_t*>(lanep + (o & ~3));
+    const uint32_t r = static_cast<uint32_t>(o & 3);
+    const uint32_t sel0 = 0x0C010C00u + r * 0x00010001u;
+    const uint32_t sel1 = sel0 + 0x00020002u;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const uint32_t lo = w[64 * m], hi = w[64 * m + 1];
+        p[2 * m] = __builtin_amdgcn_perm(hi, lo, sel0);
+        p[2 * m + 1] = __builtin_amdgcn_perm(hi, lo, sel1);
+    }
+}
+
+template <int DPW, int W, int LAYOUT>
+__global__ __launch_bounds__(64 * W) void dedisp_kernel(
+    const uint8_t* __restrict__ in, int64_t in_pitch, const int32_t* __restrict__ base,
+    const int32_t* __restrict__ offs, const DmBlock* __restrict__ blocks, int nblk, int nchan, int nchan_pad,
     int32_t* __restrict__ out, int64_t out_pitch, int64_t n_out, int row) {
-    static_assert(KS == 16, "the extraction below is written for 16 samples per lane");
+    constexpr int BD = DPW * W;
+    constexpr int CP = kChanPerPass;
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
-    constexpr int NT = 64 * WAVES;
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
     const int blk = bid % nblk;
-    const int64_t t0 = static_cast<int64_t>(bid / nblk) * (64 * KS);
+    const int64_t t0 = static_cast<int64_t>(bid / nblk) * kTimeTile;
     const DmBlock b = blocks[blk];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int ndw = min(max(b.count - wave * DPW, 0), DPW);
-    const int dfirst = b.first + wave * DPW;
+    const int32_t* bbase = base + static_cast<int64_t>(blk) * nchan_pad;
+    const int32_t* woffs = offs + static_cast<int64_t>(blk) * nchan_pad * BD + wave * DPW;
+    const int nvec = row >> 4;
 
-    uint32_t a16[DPW][KS / 2];
-    uint32_t a32[DPW][KS];
+    // Stage channel rows c0 .. c0+CP-1 into buffer `buf`. Wave w loads rows w, w+W, ...
+    auto stage = [&](int c0, int buf) {
+        uint8_t* dst = lds + buf * CP * row;
+        for (int cr = wave; cr < CP; cr += W) {
+            const int c = c0 + cr;
+            uint8_t* drow = dst + cr * row;
+            if (c < nchan) {
+                const int64_t rs = t0 + bbase[c];               // first staged sample, 16-aligned
+                const uint8_t* g = in + static_cast<int64_t>(c) * in_pitch + rs;
+                for (int v0 = 0; v0 < nvec; v0 += 64) {
+                    const int v = v0 + lane;
+                    if (v < nvec && rs + 16 * (v + 1) <= in_pitch)
+                        __builtin_amdgcn_global_load_lds(g + 16 * v, (lds_void*)(drow + 16 * v0),
+                                                         16, 0, 0);
+                }
+            } else {
+                for (int v = lane; v < nvec; v += 64) *reinterpret_cast<u32x4*>(drow + 16 * v) = u32x4{0u, 0u, 0u, 0u};
+            }
+        }
+    };
+
+    uint32_t a16[DPW][8];
+    uint32_t a32[DPW][16];
 #pragma unroll
     for (int i = 0; i < DPW; ++i) {
 #pragma unroll
-        for (int j = 0; j < KS / 2; ++j) a16[i][j] = 0;
+        for (int j = 0; j < 8; ++j) a16[i][j] = 0;
 #pragma unroll
-        for (int k = 0; k < KS; ++k) a32[i][k] = 0;
+        for (int k = 0; k < 16; ++k) a32[i][k] = 0;
     }
 
-    const int vec_per_row = row >> 4;
-    const int32_t* s_first = shifts + static_cast<int64_t>(b.first) * nchan;
+    const int npass = nchan_pad / CP;
+    stage(0, 0);
     int since_flush = 0;
-    for (int c0 = 0; c0 < nchan; c0 += CP) {
-        const int ncp = min(CP, nchan - c0);
+    for (int p = 0; p < npass; ++p) {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
-        for (int v = threadIdx.x; v < ncp * vec_per_row; v += NT) {
-            const int cr = v / vec_per_row;
-            const int k = v - cr * vec_per_row;
-            const int c = c0 + cr;
-            const int64_t g = t0 + (s_first[c] & ~15) + 16 * k;
-            u32x4 val = {0u, 0u, 0u, 0u};
-            if (g + 16 <= in_pitch) val = *reinterpret_cast<const u32x4*>(in + c * in_pitch + g);
-            *reinterpret_cast<u32x4*>(lds + cr * row + 16 * k) = val;
-        }
-        __syncthreads();
-        if (since_flush + ncp > 256) {
+        if (p + 1 < npass) stage((p + 1) * CP, (p + 1) & 1);
+        if (since_flush + CP > 256) {
 #pragma unroll
             for (int i = 0; i < DPW; ++i) {
 #pragma unroll
-                for (int j = 0; j < KS / 2; ++j) {
+                for (int j = 0; j < 8; ++j) {
                     a32[i][2 * j] += a16[i][j] & 0xFFFFu;
                     a32[i][2 * j + 1] += a16[i][j] >> 16;
                     a16[i][j] = 0;
@@ -97,74 +149,122 @@ __global__ __launch_bounds__(64 * WAVES) void dedisp_kernel(
             }
             since_flush = 0;
         }
-        since_flush += ncp;
-        for (int cr = 0; cr < ncp; ++cr) {
-            const uint8_t* rowp = lds + cr * row + 16 * lane;
+        since_flush += CP;
+        const uint8_t* bufp = lds + (p & 1) * CP * row + (LAYOUT == 0 ? 16 : 4) * lane;
+        const int32_t* po = woffs + static_cast<int64_t>(p) * CP * BD;
+        // offsets of the first channel pair; the next pair's are fetched one step ahead
+        int oa[DPW], ob[DPW];
+#pragma unroll
+        for (int i = 0; i < DPW; ++i) {
+            oa[i] = po[i];
+            ob[i] = po[BD + i];
+        }
+#pragma unroll 1
+        for (int cr = 0; cr < CP; cr += 2) {
+            const uint8_t* ra = bufp + cr * row;
+            const uint8_t* rb = ra + row;
+            int na[DPW], nb[DPW];
+            const int cn = cr + 2 < CP ? cr + 2 : cr;
+            if constexpr (LAYOUT == 0) {
+                u32x4 xa[DPW][2], xb[DPW][2];
+#pragma unroll
+                for (int i = 0; i < DPW; ++i) {
+                    const u32x4* va = reinterpret_cast<const u32x4*>(ra + (oa[i] & ~15));
+                    const u32x4* vb = reinterpret_cast<const u32x4*>(rb + (ob[i] & ~15));
+                    xa[i][0] = va[0];
+                    xa[i][1] = va[1];
+                    xb[i][0] = vb[0];
+                    xb[i][1] = vb[1];
+                }
+#pragma unroll
+                for (int i = 0; i < DPW; ++i) {
+                    na[i] = po[cn * BD + i];
+                    nb[i] = po[(cn + 1) * BD + i];
+                }
+#pragma unroll
+                for (int i = 0; i < DPW; ++i) {
+                    uint32_t pa[8], pb[8];
+                    window16(xa[i][0], xa[i][1], oa[i], pa);
+                    window16(xb[i][0], xb[i][1], ob[i], pb);
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) a16[i][j] = a16[i][j] + pa[j] + pb[j];
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < DPW; ++i) {
+                    na[i] = po[cn * BD + i];
+                    nb[i] = po[(cn + 1) * BD + i];
+                }
+#pragma unroll
+                for (int i = 0; i < DPW; ++i) {
+                    uint32_t pa[8], pb[8];
+                    window4x4(ra, oa[i], pa);
+                    window4x4(rb, ob[i], pb);
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) a16[i][j] = a16[i][j] + pa[j] + pb[j];
+                }
+            }
 #pragma unroll
             for (int i = 0; i < DPW; ++i) {
-                if (i < ndw) {
-                    const int o = offs[static_cast<int64_t>(dfirst + i) * nchan + c0 + cr];
-                    const u32x4* p = reinterpret_cast<const u32x4*>(rowp + (o & ~15));
-                    const u32x4 x0 = p[0], x1 = p[1];
-                    const uint32_t w[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
-                    const uint32_t r = static_cast<uint32_t>(o & 3);
-                    const uint32_t sel0 = 0x0C000C00u | ((r + 1u) << 16) | r;
-                    const uint32_t sel1 = sel0 + 0x00020002u;
-                    uint32_t pr[8];
-                    switch ((o >> 2) & 3) {
-                        case 0: extract16<0>(w, sel0, sel1, pr); break;
-                        case 1: extract16<1>(w, sel0, sel1, pr); break;
-                        case 2: extract16<2>(w, sel0, sel1, pr); break;
-                        default: extract16<3>(w, sel0, sel1, pr); break;
-                    }
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) a16[i][j] += pr[j];
-                }
+                oa[i] = na[i];
+                ob[i] = nb[i];
             }
         }
     }
 #pragma unroll
     for (int i = 0; i < DPW; ++i) {
 #pragma unroll
-        for (int j = 0; j < KS / 2; ++j) {
+        for (int j = 0; j < 8; ++j) {
             a32[i][2 * j] += a16[i][j] & 0xFFFFu;
             a32[i][2 * j + 1] += a16[i][j] >> 16;
         }
     }
 
-    const int64_t t = t0 + KS * lane;
 #pragma unroll
     for (int i = 0; i < DPW; ++i) {
-        if (i >= ndw) continue;
-        int32_t* o = out + static_cast<int64_t>(dfirst + i) * out_pitch + t;
-        if (t + KS <= n_out) {
+        if (wave * DPW + i >= b.count) continue;
+        int32_t* orow = out + static_cast<int64_t>(b.first + wave * DPW + i) * out_pitch;
+        // a32[i][k] holds sample t0 + 16 lane + k (contiguous layout) or
+        // t0 + 256 (k >> 2) + 4 lane + (k & 3) (interleaved layout)
 #pragma unroll
-            for (int k = 0; k < KS; k += 4) {
-                u32x4 v = {a32[i][k], a32[i][k + 1], a32[i][k + 2], a32[i][k + 3]};
-                *reinterpret_cast<u32x4*>(o + k) = v;
+        for (int g = 0; g < 4; ++g) {
+            const int64_t t = LAYOUT == 0 ? t0 + 16 * lane + 4 * g : t0 + 256 * g + 4 * lane;
+            if (t + 4 <= n_out) {
+                const u32x4 v = {a32[i][4 * g], a32[i][4 * g + 1], a32[i][4 * g + 2], a32[i][4 * g + 3]};
+                *reinterpret_cast<u32x4*>(orow + t) = v;
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (t + k < n_out) orow[t + k] = static_cast<int32_t>(a32[i][4 * g + k]);
             }
-        } else {
-#pragma unroll
-            for (int k = 0; k < KS; ++k)
-                if (t + k < n_out) o[k] = static_cast<int32_t>(a32[i][k]);
         }
     }
 }
 
+typedef void (*DedispFn)(const uint8_t*, int64_t, const int32_t*, const int32_t*, const DmBlock*, int, int, int,
+                         int32_t*, int64_t, int64_t, int);
+
+// Indexed by DedispVariant::id (tiling.cpp).
+const DedispFn kKernels[kNumDedispVariants] = {
+    dedisp_kernel<4, 4, 1>, dedisp_kernel<2, 8, 1>, dedisp_kernel<4, 8, 1>, dedisp_kernel<2, 16, 1>,
+    dedisp_kernel<2, 8, 0>, dedisp_kernel<4, 4, 0>};
+
 }  // namespace
 
-int launch_dedisperse(const aa_plan_s* p, const uint8_t* d_in, int64_t in_pitch, int64_t n_in,
+int launch_dedisperse(const aa_plan_s* p, int variant, const uint8_t* d_in, int64_t in_pitch, int64_t n_in,
                       int32_t* d_out, int64_t out_pitch, hipStream_t stream) {
+    const DedispTables& T = p->tables[variant];
+    if (T.variant != variant || !T.d_offs) return fail(AA_EINVAL, "aa_dedisperse: variant tables not prepared");
+    const DedispVariant& V = kDedispVariants[variant];
     const int64_t n_out = n_in - p->maxshift;
     const int64_t ntile = (n_out + kTimeTile - 1) / kTimeTile;
-    const int64_t nblk = static_cast<int64_t>(p->blocks.size());
+    const int64_t nblk = static_cast<int64_t>(T.blocks.size());
     const int64_t grid = ntile * nblk;
     if (grid > 0x7fffffff) return fail(AA_EINVAL, "aa_dedisperse: too many tiles for one launch");
-    const size_t lds = static_cast<size_t>(kChanPerPass) * p->max_row;
-    hipLaunchKernelGGL((dedisp_kernel<kSampPerLane, kDmPerWave, kDedispWaves, kChanPerPass>),
-                       dim3(static_cast<unsigned>(grid)), dim3(64 * kDedispWaves), lds, stream, d_in,
-                       in_pitch, p->d_shifts, p->d_offs, p->d_blocks, static_cast<int>(nblk), p->nchan,
-                       d_out, out_pitch, n_out, p->max_row);
+    const size_t lds = static_cast<size_t>(2 * kChanPerPass) * T.max_row;
+    hipLaunchKernelGGL(kKernels[variant], dim3(static_cast<unsigned>(grid)), dim3(64 * V.waves), lds, stream, d_in,
+                       in_pitch, T.d_base, T.d_offs, T.d_blocks, static_cast<int>(nblk), p->nchan, T.nchan_pad, d_out,
+                       out_pitch, n_out, T.max_row);
     AA_HIP(hipGetLastError());
     return AA_OK;
 }
@@ -182,5 +282,5 @@ extern "C" int aa_dedisperse(aa_plan_t p, const uint8_t* d_in, int64_t in_pitch,
         return fail(AA_EINVAL, "aa_dedisperse: d_in and in_pitch must be multiples of 16 bytes");
     if ((reinterpret_cast<uintptr_t>(d_out) & 15) || (out_pitch & 3) || out_pitch < n_in - p->maxshift)
         return fail(AA_EINVAL, "aa_dedisperse: d_out must be 16-byte aligned, out_pitch a multiple of 4 and >= n_out");
-    return launch_dedisperse(p, d_in, in_pitch, n_in, d_out, out_pitch, static_cast<hipStream_t>(stream));
+    return launch_dedisperse(p, p->variant, d_in, in_pitch, n_in, d_out, out_pitch, static_cast<hipStream_t>(stream));
 }

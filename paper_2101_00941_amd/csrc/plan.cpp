@@ -42,52 +42,19 @@ int64_t shift_of(double dm, double inv, double tsamp) {
 }
 
 void free_device(aa_plan_s* p) {
-    if (p->device < 0) return;
     int cur = 0;
-    (void)hipGetDevice(&cur);
-    (void)hipSetDevice(p->device);
-    if (p->d_shifts) (void)hipFree(p->d_shifts);
-    if (p->d_offs) (void)hipFree(p->d_offs);
-    if (p->d_blocks) (void)hipFree(p->d_blocks);
-    if (p->d_widths) (void)hipFree(p->d_widths);
-    (void)hipSetDevice(cur);
-    p->d_shifts = p->d_offs = p->d_widths = nullptr;
-    p->d_blocks = nullptr;
-}
-
-// Split the DM trials into blocks of at most kDmBlock consecutive trials whose staged
-// LDS rows fit kMaxRowBytes. offs[d][c] = s[d][c] - (s[first][c] & ~15) is the byte
-// offset of trial d's window inside the block's 16-byte-aligned row for channel c.
-void build_tiling(aa_plan_s* p) {
-    const int nchan = p->nchan;
-    p->offs.assign(static_cast<size_t>(p->ndm) * nchan, 0);
-    p->blocks.clear();
-    p->max_row = 0;
-    int d = 0;
-    while (d < p->ndm) {
-        const int first = d;
-        const int32_t* s0 = &p->shifts[static_cast<size_t>(first) * nchan];
-        int32_t omax = 0;
-        int count = 0;
-        while (count < kDmBlock && first + count < p->ndm) {
-            const int32_t* sd = &p->shifts[static_cast<size_t>(first + count) * nchan];
-            int32_t m = 0;
-            for (int c = 0; c < nchan; ++c) m = std::max(m, sd[c] - (s0[c] & ~15));
-            const int32_t row = kTimeTile + 16 + (std::max(omax, m) & ~15);
-            if (count > 0 && row > kMaxRowBytes) break;
-            omax = std::max(omax, m);
-            ++count;
-        }
-        for (int i = 0; i < count; ++i) {
-            const int32_t* sd = &p->shifts[static_cast<size_t>(first + i) * nchan];
-            int32_t* od = &p->offs[static_cast<size_t>(first + i) * nchan];
-            for (int c = 0; c < nchan; ++c) od[c] = sd[c] - (s0[c] & ~15);
-        }
-        DmBlock b{first, count, kTimeTile + 16 + (omax & ~15), 0};
-        p->max_row = std::max(p->max_row, b.row);
-        p->blocks.push_back(b);
-        d += count;
+    const bool on_dev = p->device >= 0;
+    if (on_dev) {
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(p->device);
     }
+    for (auto& t : p->tables) free_tables(t);
+    if (on_dev) {
+        if (p->d_shifts) (void)hipFree(p->d_shifts);
+        if (p->d_widths) (void)hipFree(p->d_widths);
+        (void)hipSetDevice(cur);
+    }
+    p->d_shifts = p->d_widths = nullptr;
 }
 
 template <class T>
@@ -190,7 +157,6 @@ extern "C" int aa_plan(const aa_plan_desc_t* desc, aa_plan_t* out) {
         return fail(AA_ESHORT, "aa_plan: nsamp < maxshift + widest boxcar");
     }
     p->nblocks = (p->n_start + B - 1) / B;
-    build_tiling(p);
 
     if (!(q.flags & AA_PLAN_HOST_ONLY)) {
         int dev = 0;
@@ -201,9 +167,15 @@ extern "C" int aa_plan(const aa_plan_desc_t* desc, aa_plan_t* out) {
         }
         p->device = dev;
         int rc = upload(&p->d_shifts, p->shifts.data(), p->shifts.size());
-        if (rc == AA_OK) rc = upload(&p->d_offs, p->offs.data(), p->offs.size());
-        if (rc == AA_OK) rc = upload(&p->d_blocks, p->blocks.data(), p->blocks.size());
         if (rc == AA_OK) rc = upload(&p->d_widths, p->widths.data(), p->widths.size());
+        if (rc != AA_OK) {
+            free_device(p);
+            delete p;
+            return rc;
+        }
+    }
+    {
+        const int rc = prepare_variant(p, p->variant);
         if (rc != AA_OK) {
             free_device(p);
             delete p;

@@ -51,6 +51,7 @@ DEDISP_CASES = [
 
 @pytest.mark.parametrize("case", range(len(DEDISP_CASES)))
 def test_dedisp_shapes_bit_exact(case):
+    from paper_2101_00941_amd import Plan
     nchan, nsamp, f_top, foff, tsamp, dms = DEDISP_CASES[case]
     say(f"dedisp case {case}: nchan {nchan} nsamp {nsamp} ndm {len(dms)}")
     rng = np.random.default_rng(case)
@@ -58,11 +59,39 @@ def test_dedisp_shapes_bit_exact(case):
     p = _plan(nchan, nsamp, f_top, foff, tsamp, dms, [1, 2], 1e9)
     s = p.shifts().astype(np.int64)
     want = oracle.dedisperse(x, s, nsamp)
-    for pitch in (None, (nsamp + 255) // 256 * 256 + 512):
-        xd = to_device(x, nsamp, pitch)
-        D = p.dedisperse(xd, n_in=nsamp)
-        got = D[:, :want.shape[1]].cpu().numpy().astype(np.int64)
-        assert np.array_equal(got, want), (case, pitch)
+    for v in range(len(Plan.variants())):
+        p.set_variant(v)
+        for pitch in (None, (nsamp + 255) // 256 * 256 + 512):
+            xd = to_device(x, nsamp, pitch)
+            D = p.dedisperse(xd, n_in=nsamp)
+            got = D[:, :want.shape[1]].cpu().numpy().astype(np.int64)
+            assert np.array_equal(got, want), (case, v, pitch)
+
+
+def test_autotune_selects_a_variant_and_stays_exact(tmp_path, monkeypatch):
+    import torch
+    from paper_2101_00941_amd import Plan
+    monkeypatch.setenv("AA_TUNE_CACHE", str(tmp_path / "tune.json"))
+    nchan, nsamp = 256, 70000
+    rng = np.random.default_rng(3)
+    x = rng.integers(0, 256, (nchan, nsamp), dtype=np.uint8)
+    dms = dm_plan(300)
+    p = _plan(nchan, nsamp, 1450.0, 300.0 / nchan, 64e-6, dms, [1], 1e9)
+    xd = to_device(x, nsamp)
+    ms = p.autotune(xd, n_in=nsamp, reps=1)
+    say(f"autotune ms per variant: {ms}, chose {p.variant}")
+    assert len(ms) == len(Plan.variants()) and all(m > 0 for m in ms)
+    assert ms[p.variant] == min(ms)
+    want = oracle.dedisperse_rows(x, p.shifts().astype(np.int64), [0, 150, 299], nsamp)
+    D = p.dedisperse(xd, n_in=nsamp)
+    torch.cuda.synchronize()
+    got = D[[0, 150, 299], :want.shape[1]].cpu().numpy().astype(np.int64)
+    assert np.array_equal(got, want)
+    # second call: the cached choice is used without timing
+    q = _plan(nchan, nsamp, 1450.0, 300.0 / nchan, 64e-6, dms, [1], 1e9)
+    ms2 = q.autotune(xd, n_in=nsamp, reps=1)
+    assert all(m == -1.0 for m in ms2) and q.variant == p.variant
+    assert '"' in (tmp_path / "tune.json").read_text()
 
 
 def test_dedisp_saturated_input_exact():
