@@ -186,6 +186,84 @@ int aa_single_pulse(aa_plan_t plan, const int32_t* d_dd, int64_t dd_pitch, int64
                     void* d_work, size_t work_bytes, aa_candidate_t* d_cand, int32_t cap,
                     int32_t* d_count, float* d_best, int64_t best_pitch, void* stream);
 
+/* ---- streamed pipeline and serving loop (A1, A6, A7) ---------------------------
+ * Section 1 (Fig. 2) of the paper splits the signal into time chunks and splits each
+ * chunk again, once per stream, with every piece tagged with its stream. Section 2
+ * gives the recipe: create the streams up front, pin host memory, use asynchronous
+ * copies tagged with a stream, and make every synchronisation non-blocking. Section
+ * 2.2 moves the search's allocations out of the loop. So does this pipeline: all
+ * device memory comes from one arena of `hbm_budget` bytes, allocated at create.
+ *
+ * A pipeline serves one or more beams. A beam is an independent signal with its own
+ * plan. A submit appends `nsamp` new samples to a beam. Only the new samples cross
+ * PCIe. The pipeline keeps each beam's overlap tail (maxshift + wmax + stat_block
+ * samples at most) on the device, and copies it device-to-device ahead of the next
+ * chunk. A submit covers the starts [e, e') that have become computable:
+ * e' = floor((R - wmax - maxshift) / stat_block) * stat_block, where R is the number of
+ * samples received so far. With AA_SUBMIT_LAST, e' = T = R - maxshift - wmax + 1 and
+ * the beam is finished. [e, e') is split into up to `nstreams` block-aligned
+ * sub-chunks on the compute streams. H2D and D2D copies run on a copy stream.
+ * Concatenated over a beam's chunks, the candidates equal those of a single
+ * whole-signal aa_dedisperse + aa_single_pulse run.
+ *
+ * Requests queue on the host. A scheduler thread admits them in arrival order, and
+ * in order per beam, when arena memory and a result slot are free. Chunks of
+ * different beams therefore overlap on the GPU. aa_poll returns finished chunks.
+ * h_chunk must be pinned (hipHostMalloc, or torch pin_memory) and stay untouched
+ * until its tag has been returned by aa_poll. submit, poll and release are
+ * thread-safe. destroy drains all work in flight.
+ * Flags: AA_PIPE_SERIAL puts copies and kernels on one stream, with no overlap (the
+ * plain single-stream baseline). AA_PIPE_TIMING records HIP-event times for copies
+ * and kernels; aa_pipeline_stats reports them.
+ */
+#define AA_PIPE_SERIAL 1u
+#define AA_PIPE_TIMING 2u
+#define AA_SUBMIT_LAST 1u
+
+typedef struct aa_pipeline_s* aa_pipeline_t;
+
+typedef struct {
+    int32_t  nstreams;      /* compute streams, 1..16 (sub-chunks per chunk)                   */
+    int32_t  max_beams;     /* beams that can be added                                         */
+    int64_t  max_chunk;     /* largest nsamp of one submit                                     */
+    int32_t  cand_cap;      /* candidate capacity per sub-chunk (0 means 65536)                */
+    int32_t  result_slots;  /* sub-chunks in flight at once (0 means 4 * nstreams)            */
+    int64_t  hbm_budget;    /* arena bytes (0: size for one chunk per stream + all histories) */
+    uint32_t flags;         /* AA_PIPE_SERIAL | AA_PIPE_TIMING                                 */
+} aa_pipeline_opts_t;
+
+typedef struct {
+    uint64_t tag;
+    int32_t  beam;
+    int32_t  status;        /* AA_OK, AA_EOVERFLOW (a sub-chunk exceeded cand_cap) or AA_EHIP */
+    int64_t  t_begin, t_end;/* absolute starts covered (t_end == t_begin: none yet)         */
+    int64_t  n_true;        /* true number of candidates                                     */
+    int64_t  n;             /* candidates in cand[] (less than n_true only on overflow)      */
+    const aa_candidate_t* cand;  /* sorted (dm_idx, t), beam set; valid until aa_release(tag) */
+    double   latency_s;     /* submit call to completion seen by the scheduler (host clock) */
+    double   queue_s;       /* submit call to admission                                      */
+} aa_result_t;
+
+typedef struct {
+    int64_t submitted, completed, in_flight, queued;
+    int64_t arena_bytes, arena_used, arena_peak;
+    /* with AA_PIPE_TIMING: union lengths (ms) of copy intervals, kernel intervals and
+     * their intersection, plus the first-to-last span; hidden = overlap / copy */
+    double  copy_ms, kernel_ms, overlap_ms, span_ms, copy_sum_ms, kernel_sum_ms;
+} aa_pipeline_stats_t;
+
+int aa_pipeline_create(const aa_pipeline_opts_t* opts, aa_pipeline_t* out);
+/* Registers a beam with its plan (created on the pipeline's device). Plan-time call:
+ * allocates the beam's history from the arena. Returns the beam id in *beam. */
+int aa_pipeline_add_beam(aa_pipeline_t pipe, aa_plan_t plan, int32_t* beam);
+int aa_stream_submit(aa_pipeline_t pipe, int32_t beam, const uint8_t* h_chunk, int64_t nsamp, int64_t pitch,
+                     uint64_t tag, uint32_t flags);
+/* Waits up to timeout_us (0: no wait, <0: forever) for a finished chunk. AA_EAGAIN if none. */
+int aa_poll(aa_pipeline_t pipe, aa_result_t* out, int32_t timeout_us);
+int aa_release(aa_pipeline_t pipe, uint64_t tag);
+int aa_pipeline_stats(aa_pipeline_t pipe, aa_pipeline_stats_t* out);
+int aa_pipeline_destroy(aa_pipeline_t pipe);
+
 #ifdef __cplusplus
 }
 #endif

@@ -41,6 +41,29 @@ class VariantInfo(C.Structure):
                 ("trials_per_block", C.c_int32), ("lds_bytes", C.c_int32), ("layout", C.c_int32)]
 
 
+class PipelineOpts(C.Structure):
+    _fields_ = [("nstreams", C.c_int32), ("max_beams", C.c_int32), ("max_chunk", C.c_int64),
+                ("cand_cap", C.c_int32), ("result_slots", C.c_int32), ("hbm_budget", C.c_int64),
+                ("flags", C.c_uint32)]
+
+
+class Result(C.Structure):
+    _fields_ = [("tag", C.c_uint64), ("beam", C.c_int32), ("status", C.c_int32), ("t_begin", C.c_int64),
+                ("t_end", C.c_int64), ("n_true", C.c_int64), ("n", C.c_int64), ("cand", C.c_void_p),
+                ("latency_s", C.c_double), ("queue_s", C.c_double)]
+
+
+class PipelineStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("in_flight", C.c_int64),
+                ("queued", C.c_int64), ("arena_bytes", C.c_int64), ("arena_used", C.c_int64),
+                ("arena_peak", C.c_int64), ("copy_ms", C.c_double), ("kernel_ms", C.c_double),
+                ("overlap_ms", C.c_double), ("span_ms", C.c_double), ("copy_sum_ms", C.c_double),
+                ("kernel_sum_ms", C.c_double)]
+
+
+AA_PIPE_SERIAL, AA_PIPE_TIMING, AA_SUBMIT_LAST = 1, 2, 1
+
+
 class AAError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
@@ -77,6 +100,13 @@ def lib():
         "aa_plan_set_variant": (C.c_int, [vp, i32]),
         "aa_plan_get_variant": (C.c_int, [vp, C.POINTER(i32)]),
         "aa_autotune": (C.c_int, [vp, vp, i64, i64, vp, i64, i32, vp, C.POINTER(C.c_float)]),
+        "aa_pipeline_create": (C.c_int, [C.POINTER(PipelineOpts), C.POINTER(vp)]),
+        "aa_pipeline_add_beam": (C.c_int, [vp, vp, C.POINTER(i32)]),
+        "aa_stream_submit": (C.c_int, [vp, i32, vp, i64, i64, C.c_uint64, C.c_uint32]),
+        "aa_poll": (C.c_int, [vp, C.POINTER(Result), i32]),
+        "aa_release": (C.c_int, [vp, C.c_uint64]),
+        "aa_pipeline_stats": (C.c_int, [vp, C.POINTER(PipelineStats)]),
+        "aa_pipeline_destroy": (C.c_int, [vp]),
         "aa_single_pulse": (C.c_int, [vp, vp, i64, i64, i64, i64, i64, i64, vp, sz, vp, i32, vp, vp, i64, vp]),
     }
     for name, (res, args) in sig.items():

@@ -192,3 +192,76 @@ def candidates_to_numpy(cand, count, cap=None):
 
 def candidates_as_tuples(arr):
     return [(int(r["dm_idx"]), int(r["t"]), int(r["width"]), float(r["snr"])) for r in arr]
+
+
+class Pipeline:
+    """aa_pipeline_*: streamed chunks over HIP streams with per-beam device tails.
+
+    submit() takes pinned host memory: a torch uint8 tensor made with pin_memory(), or
+    a numpy view of one. The memory must stay untouched until poll() has returned
+    the chunk's tag.
+    """
+
+    def __init__(self, nstreams=4, max_beams=1, max_chunk=1 << 18, cand_cap=1 << 14, result_slots=0,
+                 hbm_budget=8 << 30, serial=False, timing=False):
+        o = N.PipelineOpts()
+        o.nstreams, o.max_beams, o.max_chunk = int(nstreams), int(max_beams), int(max_chunk)
+        o.cand_cap, o.result_slots, o.hbm_budget = int(cand_cap), int(result_slots), int(hbm_budget)
+        o.flags = (N.AA_PIPE_SERIAL if serial else 0) | (N.AA_PIPE_TIMING if timing else 0)
+        h = C.c_void_p()
+        N.check(N.lib().aa_pipeline_create(C.byref(o), C.byref(h)))
+        self._h = h
+        self._keep = {}
+        self.plans = []
+
+    def add_beam(self, plan):
+        b = C.c_int32()
+        N.check(N.lib().aa_pipeline_add_beam(self._h, plan.handle, C.byref(b)))
+        self.plans.append(plan)
+        return b.value
+
+    def submit(self, beam, host, nsamp=None, tag=0, last=False, pitch=None):
+        """host: pinned uint8 [nchan, pitch] (torch tensor or numpy view of one)."""
+        if hasattr(host, "data_ptr"):
+            ptr, rows, cols, rp = host.data_ptr(), host.shape[0], host.shape[1], host.stride(0)
+        else:
+            ptr, rows, cols, rp = host.ctypes.data, host.shape[0], host.shape[1], host.strides[0]
+        nsamp = cols if nsamp is None else int(nsamp)
+        N.check(N.lib().aa_stream_submit(self._h, int(beam), C.c_void_p(ptr), nsamp, int(pitch or rp),
+                                         int(tag), N.AA_SUBMIT_LAST if last else 0))
+        self._keep[int(tag)] = host
+
+    def poll(self, timeout_us=-1):
+        """Returns None (nothing finished in time) or a dict with a structured candidate array."""
+        r = N.Result()
+        rc = N.check(N.lib().aa_poll(self._h, C.byref(r), int(timeout_us)))
+        if rc == N.AA_EAGAIN:
+            return None
+        n = int(r.n)
+        if n:
+            buf = (C.c_uint8 * (n * 24)).from_address(r.cand)
+            cand = np.frombuffer(buf, dtype=N.CANDIDATE_DTYPE, count=n).copy()
+        else:
+            cand = np.zeros(0, dtype=N.CANDIDATE_DTYPE)
+        N.check(N.lib().aa_release(self._h, r.tag))
+        self._keep.pop(int(r.tag), None)
+        return dict(tag=int(r.tag), beam=int(r.beam), status=int(r.status), t_begin=int(r.t_begin),
+                    t_end=int(r.t_end), n_true=int(r.n_true), cand=cand, latency_s=float(r.latency_s),
+                    queue_s=float(r.queue_s))
+
+    def stats(self):
+        st = N.PipelineStats()
+        N.check(N.lib().aa_pipeline_stats(self._h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in N.PipelineStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            N.check(N.lib().aa_pipeline_destroy(self._h))
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -83,7 +83,7 @@ __device__ __forceinline__ void window4x4(const uint8_t* lanep, int o, uint32_t 
 
 template <int DPW, int W, int LAYOUT>
 __global__ __launch_bounds__(64 * W) void dedisp_kernel(
-    const uint8_t* __restrict__ in, int64_t in_pitch, const int32_t* __restrict__ base,
+    const uint8_t* __restrict__ in, int64_t in_pitch, int64_t n_in16, const int32_t* __restrict__ base,
     const int32_t* __restrict__ offs, const DmBlock* __restrict__ blocks, int nblk, int nchan, int nchan_pad,
     int32_t* __restrict__ out, int64_t out_pitch, int64_t n_out, int row) {
     constexpr int BD = DPW * W;
@@ -110,7 +110,7 @@ __global__ __launch_bounds__(64 * W) void dedisp_kernel(
                 const uint8_t* g = in + static_cast<int64_t>(c) * in_pitch + rs;
                 for (int v0 = 0; v0 < nvec; v0 += 64) {
                     const int v = v0 + lane;
-                    if (v < nvec && rs + 16 * (v + 1) <= in_pitch)
+                    if (v < nvec && rs + 16 * (v + 1) <= n_in16)
                         __builtin_amdgcn_global_load_lds(g + 16 * v, (lds_void*)(drow + 16 * v0),
                                                          16, 0, 0);
                 }
@@ -241,8 +241,8 @@ __global__ __launch_bounds__(64 * W) void dedisp_kernel(
     }
 }
 
-typedef void (*DedispFn)(const uint8_t*, int64_t, const int32_t*, const int32_t*, const DmBlock*, int, int, int,
-                         int32_t*, int64_t, int64_t, int);
+typedef void (*DedispFn)(const uint8_t*, int64_t, int64_t, const int32_t*, const int32_t*, const DmBlock*, int, int,
+                         int, int32_t*, int64_t, int64_t, int);
 
 // Indexed by DedispVariant::id (tiling.cpp).
 const DedispFn kKernels[kNumDedispVariants] = {
@@ -262,8 +262,12 @@ int launch_dedisperse(const aa_plan_s* p, int variant, const uint8_t* d_in, int6
     const int64_t grid = ntile * nblk;
     if (grid > 0x7fffffff) return fail(AA_EINVAL, "aa_dedisperse: too many tiles for one launch");
     const size_t lds = static_cast<size_t>(2 * kChanPerPass) * T.max_row;
+    // Staged reads stop at n_in rounded up to 16 bytes (<= in_pitch): nothing past a row's
+    // valid samples is needed for a stored output, and the bound keeps every load inside
+    // [d_in + c * in_pitch, + round_up(n_in, 16)) even when d_in points into a larger buffer.
+    const int64_t n_in16 = (n_in + 15) & ~int64_t{15};
     hipLaunchKernelGGL(kKernels[variant], dim3(static_cast<unsigned>(grid)), dim3(64 * V.waves), lds, stream, d_in,
-                       in_pitch, T.d_base, T.d_offs, T.d_blocks, static_cast<int>(nblk), p->nchan, T.nchan_pad, d_out,
+                       in_pitch, n_in16, T.d_base, T.d_offs, T.d_blocks, static_cast<int>(nblk), p->nchan, T.nchan_pad, d_out,
                        out_pitch, n_out, T.max_row);
     AA_HIP(hipGetLastError());
     return AA_OK;
