@@ -347,7 +347,21 @@ void aa_pipeline_s::run() {
                 ++it;
                 continue;
             }
-            if (!try_issue(r)) break;
+            if (!try_issue(r)) {
+                if (inflight.empty()) {
+                    // nothing in flight can release memory or slots: this request never fits
+                    r->status = fail(AA_ENOMEM, "pipeline: chunk needs more arena memory or result slots than exist");
+                    ++bm.issued_seq;
+                    it = queue.erase(it);
+                    r->t_admit = r->t_done = now_s();
+                    done.push_back(r);
+                    ++completed;
+                    cv_done.notify_all();
+                    progress = true;
+                    continue;
+                }
+                break;
+            }
             ++bm.issued_seq;
             it = queue.erase(it);
             inflight.push_back(r);
