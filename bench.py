@@ -60,6 +60,88 @@ def cpu_baseline(w, x, n_rows=9):
                        f"dedispersion + single-pulse search, numpy, {dt:.1f} s")
 
 
+def h2d_probe(torch, nchan, ncols, pitch):
+    """PCIe host->device rate for one pinned chunk: 1-D contiguous and 2-D strided copies."""
+    dev = torch.device("cuda:0")
+    src = torch.empty((nchan, pitch), dtype=torch.uint8).pin_memory()
+    dst = torch.empty((nchan, ncols), dtype=torch.uint8, device=dev)
+    flat = torch.empty(nchan * ncols, dtype=torch.uint8).pin_memory()
+    dflat = torch.empty(nchan * ncols, dtype=torch.uint8, device=dev)
+    out = {}
+    for name, fn in (("h2d_1d_GBps", lambda: dflat.copy_(flat, non_blocking=True)),
+                     ("h2d_2d_GBps", lambda: dst.copy_(src[:, :ncols], non_blocking=True))):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(5):
+            fn()
+        torch.cuda.synchronize()
+        out[name] = 5 * nchan * ncols / (time.perf_counter() - t) / 1e9
+    return out
+
+
+def streamed(a):
+    """Streamed mode: a pinned host signal fed chunk by chunk through aa_stream_submit.
+    Runs the plain single-stream pipeline and then S = 1, 2, 4, 8 compute streams, and
+    reports end-to-end rates, copy/kernel/overlap time and the hidden-transfer share."""
+    import torch
+
+    from paper_2101_00941_amd import Pipeline, Plan
+    from synth.workloads import make_input, workload
+
+    w = workload(a.workload)
+    if a.ndm:
+        w["dms"] = w["dms"][:a.ndm]
+    chunk = w.get("chunk", 1 << 18)
+    nsamp, nchan = w["nsamp"], w["nchan"]
+    log(f"[bench] streamed {w['name']}: {nchan} x {nsamp}, chunks of {chunk}")
+    host = torch.empty((nchan, nsamp), dtype=torch.uint8).pin_memory()
+    make_input(w, out=host.numpy())
+    torch.cuda.set_device(0)
+    probe = h2d_probe(torch, nchan, chunk, nsamp)
+    log(f"[bench] H2D probe {probe}")
+    plan = Plan.from_workload(w)
+    ndm = plan.info["ndm"]
+    budget = int(a.budget_gb * (1 << 30))
+    rows = []
+    for mode, S in [("plain", 1)] + [("streams", s) for s in (1, 2, 4, 8)]:
+        best = None
+        for rep in range(2):   # first pass warms up copy engines and kernels
+            pipe = Pipeline(nstreams=S, max_beams=1, max_chunk=chunk, cand_cap=a.stream_cap, hbm_budget=budget,
+                            serial=(mode == "plain"), timing=True)
+            b = pipe.add_beam(plan)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            nk = 0
+            for k, s0 in enumerate(range(0, nsamp, chunk)):
+                n = min(chunk, nsamp - s0)
+                pipe.submit(b, host[:, s0:s0 + n], nsamp=n, pitch=nsamp, tag=k, last=(s0 + n == nsamp))
+                nk += 1
+            ncand = 0
+            for _ in range(nk):
+                r = pipe.poll(timeout_us=60_000_000)
+                assert r is not None and r["status"] in (0, -5), r
+                ncand += r["n_true"]
+            wall = time.perf_counter() - t0
+            st = pipe.stats()
+            pipe.close()
+            best = dict(mode=mode, nstreams=S, wall_ms=wall * 1e3, candidates=ncand, **st)
+        T = plan.info["n_start"]
+        best["dm_trial_samples_per_s"] = ndm * (nsamp - plan.info["maxshift"]) / (best["wall_ms"] * 1e-3)
+        best["samples_per_s"] = nsamp / (best["wall_ms"] * 1e-3)
+        best["hidden_frac"] = best["overlap_ms"] / best["copy_ms"] if best["copy_ms"] > 0 else None
+        best["efficiency"] = (max(best["copy_sum_ms"], best["kernel_sum_ms"]) / best["span_ms"]
+                              if best["span_ms"] > 0 else None)
+        rows.append(best)
+        log(f"[bench] {mode} S={S}: {best['wall_ms']:.1f} ms wall, copy {best['copy_ms']:.1f} ms, "
+            f"kernels {best['kernel_ms']:.1f} ms, overlap {best['overlap_ms']:.1f} ms, "
+            f"hidden {best['hidden_frac']}, {best['candidates']} candidates")
+    plain = rows[0]["wall_ms"]
+    for r in rows:
+        r["speedup_vs_plain"] = plain / r["wall_ms"]
+    return dict(workload=w["name"], chunk=chunk, ndm=ndm, nchan=nchan, nsamp=nsamp, h2d_probe=probe, runs=rows)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,11 +152,18 @@ def main():
     ap.add_argument("--cap", type=int, default=1 << 20)
     ap.add_argument("--variant", default="auto", help="dedispersion kernel variant, or 'auto' (autotuner)")
     ap.add_argument("--ndm", type=int, default=0, help="use only the first NDM trials (profiling runs)")
+    ap.add_argument("--mode", default="resident", choices=["resident", "streamed"])
+    ap.add_argument("--budget-gb", type=float, default=16.0)
+    ap.add_argument("--stream-cap", type=int, default=1 << 14)
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": a.gpus}), flush=True)
         sys.exit(2)
+
+    if a.mode == "streamed":
+        print(json.dumps(streamed(a)), flush=True)
+        return
 
     import torch
 

@@ -13,6 +13,8 @@ the uint8 filterbank.
   plan (0..1998), boxcars 1..256 (powers of two), threshold 6.
 * streamed_128ch_8M: the tiny signal model at 2^23 samples. One DM-50 pulse per
   2^18-sample chunk, several of them placed on chunk and sub-chunk edges.
+* survey_4096ch_1M_streamed: the survey signal fed in 2^18-sample chunks, where
+  compute outweighs the PCIe transfer.
 * batched_64beams and serving_32beams: see `batched_beams` and `serving_beams`.
 """
 
@@ -58,7 +60,14 @@ def _streamed():
     return w
 
 
-WORKLOADS = {"tiny_128ch_32k": _tiny, "survey_4096ch_1M": _survey, "streamed_128ch_8M": _streamed}
+def _survey_streamed():
+    w = _survey()
+    w.update(name="survey_4096ch_1M_streamed", chunk=1 << 18, streams=[1, 2, 4, 8])
+    return w
+
+
+WORKLOADS = {"tiny_128ch_32k": _tiny, "survey_4096ch_1M": _survey, "streamed_128ch_8M": _streamed,
+             "survey_4096ch_1M_streamed": _survey_streamed}
 
 
 def workload(name: str) -> dict:
