@@ -104,11 +104,12 @@ def streamed(a):
     ndm = plan.info["ndm"]
     budget = int(a.budget_gb * (1 << 30))
     rows = []
-    for mode, S in [("plain", 1)] + [("streams", s) for s in (1, 2, 4, 8)]:
+    modes = [("plain", 1, False)] + [("streams", s, False) for s in (1, 2, 4, 8)] + [("streams-sdma", 2, True)]
+    for mode, S, sdma in modes:
         best = None
         for rep in range(2):   # first pass warms up copy engines and kernels
             pipe = Pipeline(nstreams=S, max_beams=1, max_chunk=chunk, cand_cap=a.stream_cap, hbm_budget=budget,
-                            serial=(mode == "plain"), timing=True)
+                            serial=(mode == "plain"), timing=True, sdma_copy=sdma)
             b = pipe.add_beam(plan)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -139,7 +140,8 @@ def streamed(a):
     plain = rows[0]["wall_ms"]
     for r in rows:
         r["speedup_vs_plain"] = plain / r["wall_ms"]
-    return dict(workload=w["name"], chunk=chunk, ndm=ndm, nchan=nchan, nsamp=nsamp, h2d_probe=probe, runs=rows)
+    return dict(workload=w["name"], chunk=chunk, ndm=ndm, nchan=nchan, nsamp=nsamp, h2d_probe=probe,
+                hw_queues=os.environ.get("GPU_MAX_HW_QUEUES", "default"), runs=rows)
 
 
 def main():
@@ -155,7 +157,11 @@ def main():
     ap.add_argument("--mode", default="resident", choices=["resident", "streamed"])
     ap.add_argument("--budget-gb", type=float, default=16.0)
     ap.add_argument("--stream-cap", type=int, default=1 << 14)
+    ap.add_argument("--hw-queues", type=int, default=0, help="GPU_MAX_HW_QUEUES for this process (<= 32)")
     a = ap.parse_args()
+    if a.hw_queues:
+        # HIP maps streams onto this many hardware queues; it must be set before HIP starts
+        os.environ["GPU_MAX_HW_QUEUES"] = str(min(a.hw_queues, 32))
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": a.gpus}), flush=True)

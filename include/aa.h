@@ -212,12 +212,16 @@ int aa_single_pulse(aa_plan_t plan, const int32_t* d_dd, int64_t dd_pitch, int64
  * h_chunk must be pinned (hipHostMalloc, or torch pin_memory) and stay untouched
  * until its tag has been returned by aa_poll. submit, poll and release are
  * thread-safe. destroy drains all work in flight.
+ * H2D: when h_chunk, pitch and the destination column are 16-byte aligned, a row-gather
+ * kernel reads the mapped pinned rows directly. Otherwise, or with AA_PIPE_SDMA_COPY,
+ * hipMemcpy2DAsync is used.
  * Flags: AA_PIPE_SERIAL puts copies and kernels on one stream, with no overlap (the
  * plain single-stream baseline). AA_PIPE_TIMING records HIP-event times for copies
  * and kernels; aa_pipeline_stats reports them.
  */
 #define AA_PIPE_SERIAL 1u
 #define AA_PIPE_TIMING 2u
+#define AA_PIPE_SDMA_COPY 4u
 #define AA_SUBMIT_LAST 1u
 
 typedef struct aa_pipeline_s* aa_pipeline_t;

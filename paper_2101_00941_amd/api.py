@@ -203,11 +203,12 @@ class Pipeline:
     """
 
     def __init__(self, nstreams=4, max_beams=1, max_chunk=1 << 18, cand_cap=1 << 14, result_slots=0,
-                 hbm_budget=8 << 30, serial=False, timing=False):
+                 hbm_budget=8 << 30, serial=False, timing=False, sdma_copy=False):
         o = N.PipelineOpts()
         o.nstreams, o.max_beams, o.max_chunk = int(nstreams), int(max_beams), int(max_chunk)
         o.cand_cap, o.result_slots, o.hbm_budget = int(cand_cap), int(result_slots), int(hbm_budget)
-        o.flags = (N.AA_PIPE_SERIAL if serial else 0) | (N.AA_PIPE_TIMING if timing else 0)
+        o.flags = ((N.AA_PIPE_SERIAL if serial else 0) | (N.AA_PIPE_TIMING if timing else 0)
+                   | (N.AA_PIPE_SDMA_COPY if sdma_copy else 0))
         h = C.c_void_p()
         N.check(N.lib().aa_pipeline_create(C.byref(o), C.byref(h)))
         self._h = h

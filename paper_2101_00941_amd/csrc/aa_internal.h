@@ -96,6 +96,8 @@ void free_tables(DedispTables& t);
 int launch_dedisperse(const aa_plan_s* p, int variant, const uint8_t* d_in, int64_t in_pitch, int64_t n_in,
                       int32_t* d_out, int64_t out_pitch, hipStream_t stream);
 size_t sps_work_bytes(const aa_plan_s* p, int64_t n_starts);
+int launch_gather_rows(uint8_t* dst, int64_t dpitch, const uint8_t* src, int64_t spitch, int64_t width,
+                       int64_t nrows, hipStream_t stream);
 int launch_single_pulse(const aa_plan_s* p, const int32_t* d_dd, int64_t dd_pitch, int64_t dd_t0,
                         int64_t dd_n, int64_t t_begin, int64_t t_end, int64_t t_total, void* d_work,
                         aa_candidate_t* d_cand, int32_t cap, int32_t* d_count, float* d_best,

@@ -144,7 +144,8 @@ bool aa_pipeline_s::try_issue(Request* r) {
     const ChunkRange cr = chunk_range(bm.e, R2, M, W, B, last);
     const int64_t e2 = cr.e2, t_total = cr.t_total;
     const std::vector<Piece> pieces = split_blocks(bm.e, e2, B, opt.nstreams);
-    const int64_t h0n = bm.e > 0 ? bm.e - 1 : 0;
+    // keep the history from the left-halo column of the next start, rounded down to 16 bytes
+    const int64_t h0n = bm.e > 0 ? ((bm.e - 1) & ~int64_t{15}) : 0;
     if (R2 - h0n > bm.cols) {
         r->status = fail(AA_EINVAL, "aa_stream_submit: chunk does not fit the beam history");
         return true;  // completes with an error below
@@ -185,16 +186,38 @@ bool aa_pipeline_s::try_issue(Request* r) {
         (void)hipMemcpy2DAsync(bm.buf[nb], bm.pitch, bm.buf[bm.cur] + (h0n - bm.h0), bm.pitch, bm.R - h0n, nchan,
                                hipMemcpyDeviceToDevice, cs);
     }
-    // H2D of the new samples in pieces; event after each
+    // H2D of the new samples in pieces, with an event after each. Mapped pinned rows are
+    // gathered by a kernel when every row start is 16-byte aligned; otherwise the
+    // runtime's 2-D copy is used.
+    const uint8_t* hdev = nullptr;
+    int64_t col = bm.R - h0n, src = 0;
+    if (!(opt.flags & AA_PIPE_SDMA_COPY) && r->n > 0 && (reinterpret_cast<uintptr_t>(r->h) & 15) == 0 &&
+        (r->pitch & 15) == 0 && (col & 15) == 0 && (bm.pitch & 15) == 0) {
+        void* dp = nullptr;
+        if (hipHostGetDevicePointer(&dp, const_cast<uint8_t*>(r->h), 0) == hipSuccess && dp)
+            hdev = static_cast<const uint8_t*>(dp);
+        else
+            (void)hipGetLastError();
+    }
     const int npc = std::max<int>(1, std::min<int>(opt.nstreams, static_cast<int>((r->n + 4095) / 4096)));
     std::vector<hipEvent_t> pev;
     std::vector<int64_t> pend;   // end column (exclusive) covered after piece i
-    int64_t col = bm.R - h0n, src = 0;
     for (int i = 0; i < npc; ++i) {
-        const int64_t w = r->n / npc + (i < r->n % npc ? 1 : 0);
-        if (w > 0)
-            (void)hipMemcpy2DAsync(bm.buf[nb] + col, bm.pitch, r->h + src, r->pitch, w, nchan, hipMemcpyHostToDevice,
-                                   cs);
+        int64_t w = (r->n - src) / (npc - i);
+        if (i + 1 < npc) w &= ~int64_t{15};
+        else w = r->n - src;
+        if (w > 0) {
+            if (hdev && (w & 15) == 0)
+                (void)launch_gather_rows(bm.buf[nb] + col, bm.pitch, hdev + src, r->pitch, w, nchan, cs);
+            else if (hdev) {   // 16-byte body by the kernel, ragged tail by the runtime copy
+                const int64_t body = w & ~int64_t{15};
+                if (body) (void)launch_gather_rows(bm.buf[nb] + col, bm.pitch, hdev + src, r->pitch, body, nchan, cs);
+                (void)hipMemcpy2DAsync(bm.buf[nb] + col + body, bm.pitch, r->h + src + body, r->pitch, w - body, nchan,
+                                       hipMemcpyHostToDevice, cs);
+            } else
+                (void)hipMemcpy2DAsync(bm.buf[nb] + col, bm.pitch, r->h + src, r->pitch, w, nchan,
+                                       hipMemcpyHostToDevice, cs);
+        }
         col += w;
         src += w;
         hipEvent_t ev = get_event(false);

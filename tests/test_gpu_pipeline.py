@@ -35,11 +35,11 @@ def sig():
     return dict(x=x, host=host, nchan=nchan, nsamp=nsamp, dms=dms, want=want)
 
 
-def _run(sig, chunk, nstreams, serial=False, cap=1 << 14):
+def _run(sig, chunk, nstreams, serial=False, cap=1 << 14, sdma=False):
     from paper_2101_00941_amd import Pipeline, Plan
     plan = Plan(sig["nchan"], sig["nsamp"], F_TOP, FOFF, TSAMP, sig["dms"], WIDTHS, 6.0, 32768)
     pipe = Pipeline(nstreams=nstreams, max_beams=1, max_chunk=chunk, cand_cap=cap, hbm_budget=2 << 30,
-                    serial=serial, timing=True)
+                    serial=serial, timing=True, sdma_copy=sdma)
     b = pipe.add_beam(plan)
     host, nsamp = sig["host"], sig["nsamp"]
     tags = []
@@ -77,9 +77,14 @@ def test_streamed_equals_whole_signal(sig, nstreams, serial):
     say(f"  copy {st['copy_ms']:.2f} ms, kernels {st['kernel_ms']:.2f} ms, overlap {st['overlap_ms']:.2f} ms")
 
 
-@pytest.mark.parametrize("chunk", [100_000, 40_000, 250_000])
+@pytest.mark.parametrize("chunk", [100_000, 40_000, 250_000, 99_999])
 def test_odd_chunk_sizes(sig, chunk):
     got, _, _ = _run(sig, chunk, 4)
+    assert_candidates_equal(got, sig["want"])
+
+
+def test_runtime_copy_path_matches(sig):
+    got, _, _ = _run(sig, 1 << 17, 2, sdma=True)
     assert_candidates_equal(got, sig["want"])
 
 

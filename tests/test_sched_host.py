@@ -62,7 +62,7 @@ static void test_ranges(unsigned seed) {
             const int64_t n = std::min<int64_t>(total - R, 1 + rng() % max_chunk);
             const int64_t R2 = R + n;
             const bool last = R2 == total;
-            const int64_t h0n = e > 0 ? e - 1 : 0;
+            const int64_t h0n = e > 0 ? ((e - 1) & ~int64_t{15}) : 0;
             CHECK(R2 - h0n <= max_chunk + M + W + B + 32);           // history capacity
             ChunkRange c = chunk_range(e, R2, M, W, B, last);
             CHECK(c.e2 >= e);
