@@ -144,6 +144,136 @@ def streamed(a):
                 hw_queues=os.environ.get("GPU_MAX_HW_QUEUES", "default"), runs=rows)
 
 
+def serving(a):
+    """Serving loop: 32 beams emit 2^17-sample chunks at Poisson times (0.5-2x real time,
+    times `--rate-scale`). The continuous-batching pipeline (S compute streams, HBM-budget
+    admission, device tails) is compared with the plain path (one stream, FIFO) on the
+    same arrivals. Reports p50/p99 chunk latency (submit to result) and sustained rates."""
+    import torch
+
+    from paper_2101_00941_amd import Pipeline, Plan
+    from synth.filterbank import Pulse, make_filterbank
+    from synth.workloads import poisson_arrivals, serving_beams
+
+    beams = serving_beams(nbeams=a.beams)
+    chunk, nchan = beams[0]["chunk"], beams[0]["nchan"]
+    torch.cuda.set_device(0)
+    npool = 6
+    log(f"[bench] serving: {len(beams)} beams, chunks of {chunk} x {nchan}, pool of {npool} chunks")
+    pool = []
+    for k in range(npool):
+        h = torch.empty((nchan, chunk), dtype=torch.uint8).pin_memory()
+        make_filterbank(nchan, chunk, 1450.0, 300.0 / 4096, 64e-6, [Pulse(300.0 + 100 * k, 60000.0, 8.0, 8.0)],
+                        seed=100 + k, out=h.numpy())
+        pool.append(h)
+    plans = [Plan(nchan, 1 << 20, b["f_top"], b["foff"], b["tsamp"], b["dms"], b["widths"], b["threshold"],
+                  b["stat_block"]) for b in beams]
+    out = {}
+    for scale in a.rate_scale:
+        arrivals = poisson_arrivals(beams, a.serve_seconds, rate_scale=scale)
+        for mode in ("continuous", "plain"):
+            pipe = Pipeline(nstreams=1 if mode == "plain" else a.serve_streams, max_beams=len(beams),
+                            max_chunk=chunk, cand_cap=a.stream_cap, hbm_budget=int(a.budget_gb * (1 << 30)),
+                            serial=(mode == "plain"), result_slots=64)
+            ids = [pipe.add_beam(p) for p in plans]
+            nxt = [0] * len(beams)
+            lat, work, done = [], 0, 0
+            t0 = time.perf_counter()
+
+            def drain(timeout):
+                nonlocal work, done
+                r = pipe.poll(timeout_us=timeout)
+                while r is not None:
+                    assert r["status"] in (0, -5), r
+                    lat.append(r["latency_s"])
+                    work += plans[r["beam"]].info["ndm"] * (r["t_end"] - r["t_begin"])
+                    done += 1
+                    r = pipe.poll(timeout_us=0)
+
+            for i, (ta, b) in enumerate(arrivals):
+                while True:
+                    dt = ta - (time.perf_counter() - t0)
+                    if dt <= 0:
+                        break
+                    drain(int(min(dt, 0.01) * 1e6))
+                pipe.submit(ids[b], pool[(b + nxt[b]) % npool], nsamp=chunk, tag=i)
+                nxt[b] += 1
+            while done < len(arrivals):
+                drain(1_000_000)
+            wall = time.perf_counter() - t0
+            st = pipe.stats()
+            pipe.close()
+            lat_ms = np.array(lat) * 1e3
+            res = dict(chunks=len(arrivals), wall_s=wall, p50_ms=float(np.percentile(lat_ms, 50)),
+                       p99_ms=float(np.percentile(lat_ms, 99)), mean_ms=float(lat_ms.mean()),
+                       dm_trial_samples_per_s=work / wall, arena_peak_gb=st["arena_peak"] / 2**30)
+            out[f"x{scale:g}_{mode}"] = res
+            log(f"[bench] serving x{scale:g} {mode}: {len(arrivals)} chunks, p50 {res['p50_ms']:.1f} ms, "
+                f"p99 {res['p99_ms']:.1f} ms, {res['dm_trial_samples_per_s']:.3e} DM-trial*samples/s, "
+                f"arena peak {res['arena_peak_gb']:.1f} GB")
+    return dict(workload="serving_32beams", chunk=chunk, nchan=nchan, beams=len(beams),
+                seconds=a.serve_seconds, streams=a.serve_streams, hbm_budget_gb=a.budget_gb, results=out)
+
+
+def batched(a):
+    """Batched beams: 64 beams of uneven shape (nchan 1024/2048/4096, nsamp U[2^16, 2^20],
+    500-3000 trials) generated on the device. The per-beam plain loop (aa_dedisperse +
+    aa_single_pulse per beam) is compared with aa_batch_run (one persistent dedispersion
+    launch per group, autotuned variant). Candidate lists must be identical."""
+    import torch
+
+    from paper_2101_00941_amd import Plan, batch_run, candidates_as_tuples, candidates_to_numpy
+    from synth.filterbank_torch import make_filterbank_torch
+    from synth.workloads import batched_beams
+
+    torch.cuda.set_device(0)
+    bs = batched_beams(nbeams=a.beams)
+    t = time.perf_counter()
+    beams = []
+    for b in bs:
+        x = make_filterbank_torch(b["nchan"], b["nsamp"], b["f_top"], b["foff"], b["tsamp"], b["pulses"],
+                                  seed=b["seed"], device="cuda:0")
+        plan = Plan(b["nchan"], b["nsamp"], b["f_top"], b["foff"], b["tsamp"], b["dms"], b["widths"],
+                    b["threshold"], b["stat_block"])
+        beams.append((plan, x, b["nsamp"]))
+    torch.cuda.synchronize()
+    in_gb = sum(x.numel() for _, x, _ in beams) / 1e9
+    work_units = sum(p.info["ndm"] * p.info["n_dd"] for p, _, _ in beams)
+    log(f"[bench] batched: {len(beams)} beams, {in_gb:.1f} GB input on device, made in {time.perf_counter() - t:.1f} s")
+    cap = a.stream_cap
+    work = torch.empty(int(a.budget_gb * (1 << 30)), dtype=torch.uint8, device="cuda:0")
+    # batch (autotuned once, then timed)
+    cands, counts, info = batch_run(beams, variant=-1, work=work, cap=cap)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    cands, counts, info = batch_run(beams, variant=info["variant"], work=work, cap=cap)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t
+    log(f"[bench] batch: {t_batch * 1e3:.1f} ms ({info})")
+    # per-beam plain loop, same variant, same work buffer for the planes
+    plain_counts, plain_cands = [], []
+    t = time.perf_counter()
+    for plan, x, n in beams:
+        plan.set_variant(info["variant"])
+        opitch = (plan.info["n_dd"] + 63) // 64 * 64
+        dd = work[: plan.info["ndm"] * opitch * 4].view(torch.int32).view(plan.info["ndm"], opitch)
+        plan.dedisperse(x, n_in=n, out=dd)
+        c, cnt, _ = plan.single_pulse(dd, cap=cap)
+        plain_counts.append(cnt)
+        plain_cands.append(c)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t
+    same = True
+    for i in range(len(beams)):
+        pc = candidates_as_tuples(candidates_to_numpy(plain_cands[i], plain_counts[i], cap))
+        same &= int(plain_counts[i].item()) == int(counts[i]) and pc == candidates_as_tuples(cands[i])
+    log(f"[bench] plain loop: {t_plain * 1e3:.1f} ms; identical results: {same}")
+    return dict(workload="batched_64beams", beams=len(beams), input_gb=in_gb, dm_trial_samples=work_units,
+                batch_ms=t_batch * 1e3, plain_ms=t_plain * 1e3,
+                batch_dm_trial_samples_per_s=work_units / t_batch, plain_dm_trial_samples_per_s=work_units / t_plain,
+                identical=bool(same), info=info)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,10 +284,16 @@ def main():
     ap.add_argument("--cap", type=int, default=1 << 20)
     ap.add_argument("--variant", default="auto", help="dedispersion kernel variant, or 'auto' (autotuner)")
     ap.add_argument("--ndm", type=int, default=0, help="use only the first NDM trials (profiling runs)")
-    ap.add_argument("--mode", default="resident", choices=["resident", "streamed"])
+    ap.add_argument("--mode", default="resident", choices=["resident", "streamed", "serving", "batched"])
+    ap.add_argument("--beams", type=int, default=32)
+    ap.add_argument("--serve-seconds", type=float, default=20.0)
+    ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--rate-scale", type=float, nargs="+", default=[1.0, 4.0])
     ap.add_argument("--budget-gb", type=float, default=16.0)
     ap.add_argument("--stream-cap", type=int, default=1 << 14)
     ap.add_argument("--hw-queues", type=int, default=0, help="GPU_MAX_HW_QUEUES for this process (<= 32)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain 1 GiB device copy first (reference kernel for HBM counters)")
     a = ap.parse_args()
     if a.hw_queues:
         # HIP maps streams onto this many hardware queues; it must be set before HIP starts
@@ -169,6 +305,18 @@ def main():
 
     if a.mode == "streamed":
         print(json.dumps(streamed(a)), flush=True)
+        return
+    if a.mode == "batched":
+        if a.budget_gb == 16.0:
+            a.budget_gb = 120.0
+        if a.beams == 32:
+            a.beams = 64
+        print(json.dumps(batched(a)), flush=True)
+        return
+    if a.mode == "serving":
+        if a.budget_gb == 16.0:
+            a.budget_gb = 200.0
+        print(json.dumps(serving(a)), flush=True)
         return
 
     import torch
@@ -219,6 +367,12 @@ def main():
         h_count.copy_(count, non_blocking=True)
         h_cand.copy_(cand, non_blocking=True)
 
+    if a.calibrate_copy:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for i in range(a.warmup):
         step()
         log(f"[bench] warmup {i + 1}/{a.warmup}")

@@ -186,6 +186,41 @@ int aa_single_pulse(aa_plan_t plan, const int32_t* d_dd, int64_t dd_pitch, int64
                     void* d_work, size_t work_bytes, aa_candidate_t* d_cand, int32_t cap,
                     int32_t* d_count, float* d_best, int64_t best_pitch, void* stream);
 
+/* ---- batched beams in one persistent launch ---------------------------------------
+ * Many independent beams of uneven shape (nchan, nsamp, DM plan) are searched together.
+ * The dedispersion of every beam in a group is ONE persistent launch: resident
+ * work-groups pull (beam, DM block, time tile) items from a device counter. Each beam's
+ * single-pulse search follows on the same stream. Beams are packed into groups whose
+ * planes and search scratch fit d_work. Results equal per-beam aa_dedisperse +
+ * aa_single_pulse runs over the whole input (t_begin 0, t_end = t_total = T).
+ * variant: the dedispersion kernel variant for all beams. -1 runs aa_autotune on the
+ * beam with the most work and uses its choice.
+ * d_cand: [nbeams][cap] candidates; beam i writes its list at d_cand + i*cap, with
+ * beam = i. d_count: [nbeams] true counts.
+ * The call is ordered on `stream` and returns after the work has completed.
+ * Errors: AA_EINVAL for bad beams; AA_ENOMEM if one beam's plane does not fit d_work.
+ */
+#define AA_BATCH_STATIC 1u   /* one work-group per item instead of the persistent grid */
+
+typedef struct {
+    aa_plan_t      plan;
+    const uint8_t* d_in;       /* uint8 [nchan][in_pitch], 16-byte aligned */
+    int64_t        in_pitch;
+    int64_t        n_in;       /* samples per channel */
+} aa_batch_beam_t;
+
+typedef struct {
+    int32_t groups;            /* persistent launches used */
+    int32_t variant;           /* dedispersion variant used */
+    int64_t items;             /* (beam, DM block, time tile) items over all groups */
+    float   ms_dedisp;         /* HIP-event time of the dedispersion launches */
+    float   ms_search;         /* HIP-event time of the single-pulse searches */
+} aa_batch_info_t;
+
+int aa_batch_run(const aa_batch_beam_t* beams, int32_t nbeams, int32_t variant, void* d_work, size_t work_bytes,
+                 aa_candidate_t* d_cand, int32_t cap, int32_t* d_count, uint32_t flags, aa_batch_info_t* info,
+                 void* stream);
+
 /* ---- streamed pipeline and serving loop (A1, A6, A7) ---------------------------
  * Section 1 (Fig. 2) of the paper splits the signal into time chunks and splits each
  * chunk again, once per stream, with every piece tagged with its stream. Section 2

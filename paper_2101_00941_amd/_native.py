@@ -62,6 +62,16 @@ class PipelineStats(C.Structure):
 
 
 AA_PIPE_SERIAL, AA_PIPE_TIMING, AA_PIPE_SDMA_COPY, AA_SUBMIT_LAST = 1, 2, 4, 1
+AA_BATCH_STATIC = 1
+
+
+class BatchBeam(C.Structure):
+    _fields_ = [("plan", C.c_void_p), ("d_in", C.c_void_p), ("in_pitch", C.c_int64), ("n_in", C.c_int64)]
+
+
+class BatchInfo(C.Structure):
+    _fields_ = [("groups", C.c_int32), ("variant", C.c_int32), ("items", C.c_int64), ("ms_dedisp", C.c_float),
+                ("ms_search", C.c_float)]
 
 
 class AAError(RuntimeError):
@@ -107,6 +117,8 @@ def lib():
         "aa_release": (C.c_int, [vp, C.c_uint64]),
         "aa_pipeline_stats": (C.c_int, [vp, C.POINTER(PipelineStats)]),
         "aa_pipeline_destroy": (C.c_int, [vp]),
+        "aa_batch_run": (C.c_int, [C.POINTER(BatchBeam), i32, i32, vp, sz, vp, i32, vp, C.c_uint32,
+                                   C.POINTER(BatchInfo), vp]),
         "aa_single_pulse": (C.c_int, [vp, vp, i64, i64, i64, i64, i64, i64, vp, sz, vp, i32, vp, vp, i64, vp]),
     }
     for name, (res, args) in sig.items():

@@ -266,3 +266,33 @@ class Pipeline:
             self.close()
         except Exception:
             pass
+
+
+def batch_run(beams, variant=-1, work=None, work_bytes=None, cap=1 << 16, static=False, stream=None):
+    """aa_batch_run. beams: list of (Plan, uint8 CUDA tensor [nchan, pitch], n_in).
+    Returns (list of per-beam structured candidate arrays, true counts, info dict)."""
+    import torch
+    n = len(beams)
+    arr = (N.BatchBeam * n)()
+    for i, (plan, x, n_in) in enumerate(beams):
+        if x.dtype != torch.uint8 or not x.is_cuda or x.shape[0] < plan.info["nchan"] or n_in > x.shape[1]:
+            raise ValueError(f"beam {i}: input must be a uint8 CUDA tensor [nchan, >= n_in]")
+        arr[i].plan = plan.handle.value
+        arr[i].d_in = x.data_ptr()
+        arr[i].in_pitch = x.stride(0)
+        arr[i].n_in = int(n_in)
+    dev = beams[0][1].device
+    if work is None:
+        work = torch.empty(int(work_bytes), dtype=torch.uint8, device=dev)
+    cand = torch.empty(max(cap, 1) * 24 * n, dtype=torch.uint8, device=dev)
+    count = torch.zeros(n, dtype=torch.int32, device=dev)
+    info = N.BatchInfo()
+    N.check(N.lib().aa_batch_run(arr, n, int(variant), _ptr(work), work.numel(), _ptr(cand), int(cap), _ptr(count),
+                                 N.AA_BATCH_STATIC if static else 0, C.byref(info), _stream_handle(stream)))
+    counts = count.cpu().numpy().astype(np.int64)
+    raw = cand.cpu().numpy()
+    out = []
+    for i in range(n):
+        k = int(min(counts[i], cap))
+        out.append(raw[i * cap * 24:(i * cap + k) * 24].view(N.CANDIDATE_DTYPE).copy())
+    return out, counts, {k: getattr(info, k) for k, _ in N.BatchInfo._fields_}

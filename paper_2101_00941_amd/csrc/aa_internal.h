@@ -67,6 +67,18 @@ struct DedispTables {
     int32_t* d_offs = nullptr;
 };
 
+// Arguments of one dedispersion launch (one beam), passed by value or from a device table.
+struct DedispArgs {
+    const uint8_t* in;
+    int64_t in_pitch, n_in16;
+    const int32_t* base;
+    const int32_t* offs;
+    const DmBlock* blocks;
+    int32_t nblk, nchan, nchan_pad, row;
+    int32_t* out;
+    int64_t out_pitch, n_out, ntile;
+};
+
 }  // namespace aa
 
 struct aa_plan_s {
@@ -95,11 +107,15 @@ void free_tables(DedispTables& t);
 // Launchers (dedisp.hip, sps.hip). Arguments are validated by the callers.
 int launch_dedisperse(const aa_plan_s* p, int variant, const uint8_t* d_in, int64_t in_pitch, int64_t n_in,
                       int32_t* d_out, int64_t out_pitch, hipStream_t stream);
+DedispArgs dedisp_args(const aa_plan_s* p, int variant, const uint8_t* d_in, int64_t in_pitch, int64_t n_in,
+                       int32_t* d_out, int64_t out_pitch);
+int launch_dedisperse_batch(int variant, const DedispArgs* d_args, const int64_t* d_item_begin, int nbeams,
+                            int64_t total, unsigned long long* d_counter, int max_row, hipStream_t stream);
 size_t sps_work_bytes(const aa_plan_s* p, int64_t n_starts);
 int launch_gather_rows(uint8_t* dst, int64_t dpitch, const uint8_t* src, int64_t spitch, int64_t width,
                        int64_t nrows, hipStream_t stream);
 int launch_single_pulse(const aa_plan_s* p, const int32_t* d_dd, int64_t dd_pitch, int64_t dd_t0,
                         int64_t dd_n, int64_t t_begin, int64_t t_end, int64_t t_total, void* d_work,
                         aa_candidate_t* d_cand, int32_t cap, int32_t* d_count, float* d_best,
-                        int64_t best_pitch, hipStream_t stream);
+                        int64_t best_pitch, hipStream_t stream, int32_t beam_id = 0);
 }  // namespace aa

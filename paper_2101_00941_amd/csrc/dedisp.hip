@@ -81,18 +81,20 @@ __device__ __forceinline__ void window4x4(const uint8_t* lanep, int o, uint32_t 
     }
 }
 
+// One (DM block, time tile) of one beam. Used by the per-plan launch and by the
+// batched persistent launch.
 template <int DPW, int W, int LAYOUT>
-__global__ __launch_bounds__(64 * W) void dedisp_kernel(
-    const uint8_t* __restrict__ in, int64_t in_pitch, int64_t n_in16, const int32_t* __restrict__ base,
-    const int32_t* __restrict__ offs, const DmBlock* __restrict__ blocks, int nblk, int nchan, int nchan_pad,
-    int32_t* __restrict__ out, int64_t out_pitch, int64_t n_out, int row) {
+__device__ __forceinline__ void dedisp_tile(const DedispArgs& A, int blk, int64_t t0) {
     constexpr int BD = DPW * W;
     constexpr int CP = kChanPerPass;
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
-    const int bid = xcd_remap(blockIdx.x, gridDim.x);
-    const int blk = bid % nblk;
-    const int64_t t0 = static_cast<int64_t>(bid / nblk) * kTimeTile;
-    const DmBlock b = blocks[blk];
+    const uint8_t* __restrict__ in = A.in;
+    const int64_t in_pitch = A.in_pitch, n_in16 = A.n_in16, out_pitch = A.out_pitch, n_out = A.n_out;
+    const int32_t* __restrict__ base = A.base;
+    const int32_t* __restrict__ offs = A.offs;
+    const int nchan = A.nchan, nchan_pad = A.nchan_pad, row = A.row;
+    int32_t* __restrict__ out = A.out;
+    const DmBlock b = A.blocks[blk];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int32_t* bbase = base + static_cast<int64_t>(blk) * nchan_pad;
@@ -241,34 +243,108 @@ __global__ __launch_bounds__(64 * W) void dedisp_kernel(
     }
 }
 
-typedef void (*DedispFn)(const uint8_t*, int64_t, int64_t, const int32_t*, const int32_t*, const DmBlock*, int, int,
-                         int, int32_t*, int64_t, int64_t, int);
+template <int DPW, int W, int LAYOUT>
+__global__ __launch_bounds__(64 * W) void dedisp_kernel(DedispArgs a) {
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    dedisp_tile<DPW, W, LAYOUT>(a, bid % a.nblk, static_cast<int64_t>(bid / a.nblk) * kTimeTile);
+}
+
+// Batched persistent launch: a grid of resident work-groups pulls (beam, DM block,
+// time tile) items from one device counter until the items run out, so beams of any
+// shape share one launch. Consecutive items are adjacent DM blocks of the same tile
+// of the same beam (their input rows overlap). A work-group reads the item index from
+// the counter, finds its beam by binary search over item_begin, and exits when the
+// index passes the total: every work-group reaches that exit.
+template <int DPW, int W, int LAYOUT>
+__global__ __launch_bounds__(64 * W) void dedisp_batch_kernel(const DedispArgs* __restrict__ args,
+                                                              const int64_t* __restrict__ item_begin, int nbeams,
+                                                              int64_t total, unsigned long long* counter) {
+    __shared__ int64_t item;
+    for (;;) {
+        if (threadIdx.x == 0) item = static_cast<int64_t>(atomicAdd(counter, 1ull));
+        __syncthreads();
+        const int64_t it = item;
+        __syncthreads();
+        if (it >= total) break;
+        int lo = 0, hi = nbeams - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (item_begin[mid] <= it) lo = mid; else hi = mid - 1;
+        }
+        const DedispArgs a = args[lo];
+        const int64_t local = it - item_begin[lo];
+        dedisp_tile<DPW, W, LAYOUT>(a, static_cast<int>(local % a.nblk), (local / a.nblk) * kTimeTile);
+        __syncthreads();   // the next item restages LDS buffer 0
+    }
+}
+
+__global__ void reset_counter_kernel(unsigned long long* c) { *c = 0ull; }
+
+typedef void (*DedispFn)(DedispArgs);
+typedef void (*DedispBatchFn)(const DedispArgs*, const int64_t*, int, int64_t, unsigned long long*);
 
 // Indexed by DedispVariant::id (tiling.cpp).
 const DedispFn kKernels[kNumDedispVariants] = {
     dedisp_kernel<4, 4, 1>, dedisp_kernel<2, 8, 1>, dedisp_kernel<4, 8, 1>, dedisp_kernel<2, 16, 1>,
     dedisp_kernel<2, 8, 0>, dedisp_kernel<4, 4, 0>};
+const DedispBatchFn kBatchKernels[kNumDedispVariants] = {
+    dedisp_batch_kernel<4, 4, 1>, dedisp_batch_kernel<2, 8, 1>, dedisp_batch_kernel<4, 8, 1>,
+    dedisp_batch_kernel<2, 16, 1>, dedisp_batch_kernel<2, 8, 0>, dedisp_batch_kernel<4, 4, 0>};
 
 }  // namespace
+
+DedispArgs dedisp_args(const aa_plan_s* p, int variant, const uint8_t* d_in, int64_t in_pitch, int64_t n_in,
+                       int32_t* d_out, int64_t out_pitch) {
+    const DedispTables& T = p->tables[variant];
+    DedispArgs a{};
+    a.in = d_in;
+    a.in_pitch = in_pitch;
+    // Staged reads stop at n_in rounded up to 16 bytes (<= in_pitch): nothing past a row's
+    // valid samples is needed for a stored output, and the bound keeps every load inside
+    // [d_in + c * in_pitch, + round_up(n_in, 16)) even when d_in points into a larger buffer.
+    a.n_in16 = (n_in + 15) & ~int64_t{15};
+    a.base = T.d_base;
+    a.offs = T.d_offs;
+    a.blocks = T.d_blocks;
+    a.nblk = static_cast<int>(T.blocks.size());
+    a.nchan = p->nchan;
+    a.nchan_pad = T.nchan_pad;
+    a.out = d_out;
+    a.out_pitch = out_pitch;
+    a.n_out = n_in - p->maxshift;
+    a.row = T.max_row;
+    a.ntile = (a.n_out + kTimeTile - 1) / kTimeTile;
+    return a;
+}
 
 int launch_dedisperse(const aa_plan_s* p, int variant, const uint8_t* d_in, int64_t in_pitch, int64_t n_in,
                       int32_t* d_out, int64_t out_pitch, hipStream_t stream) {
     const DedispTables& T = p->tables[variant];
     if (T.variant != variant || !T.d_offs) return fail(AA_EINVAL, "aa_dedisperse: variant tables not prepared");
     const DedispVariant& V = kDedispVariants[variant];
-    const int64_t n_out = n_in - p->maxshift;
-    const int64_t ntile = (n_out + kTimeTile - 1) / kTimeTile;
-    const int64_t nblk = static_cast<int64_t>(T.blocks.size());
-    const int64_t grid = ntile * nblk;
+    const DedispArgs a = dedisp_args(p, variant, d_in, in_pitch, n_in, d_out, out_pitch);
+    const int64_t grid = a.ntile * a.nblk;
     if (grid > 0x7fffffff) return fail(AA_EINVAL, "aa_dedisperse: too many tiles for one launch");
     const size_t lds = static_cast<size_t>(2 * kChanPerPass) * T.max_row;
-    // Staged reads stop at n_in rounded up to 16 bytes (<= in_pitch): nothing past a row's
-    // valid samples is needed for a stored output, and the bound keeps every load inside
-    // [d_in + c * in_pitch, + round_up(n_in, 16)) even when d_in points into a larger buffer.
-    const int64_t n_in16 = (n_in + 15) & ~int64_t{15};
-    hipLaunchKernelGGL(kKernels[variant], dim3(static_cast<unsigned>(grid)), dim3(64 * V.waves), lds, stream, d_in,
-                       in_pitch, n_in16, T.d_base, T.d_offs, T.d_blocks, static_cast<int>(nblk), p->nchan, T.nchan_pad, d_out,
-                       out_pitch, n_out, T.max_row);
+    hipLaunchKernelGGL(kKernels[variant], dim3(static_cast<unsigned>(grid)), dim3(64 * V.waves), lds, stream, a);
+    AA_HIP(hipGetLastError());
+    return AA_OK;
+}
+
+int launch_dedisperse_batch(int variant, const DedispArgs* d_args, const int64_t* d_item_begin, int nbeams,
+                            int64_t total, unsigned long long* d_counter, int max_row, hipStream_t stream) {
+    const DedispVariant& V = kDedispVariants[variant];
+    const size_t lds = static_cast<size_t>(2 * kChanPerPass) * max_row;
+    int dev = 0, cus = 0, per_cu = 0;
+    AA_HIP(hipGetDevice(&dev));
+    AA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    AA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kBatchKernels[variant], 64 * V.waves, lds));
+    if (per_cu < 1) return fail(AA_EINVAL, "batched dedispersion: the kernel does not fit on a CU");
+    const int64_t grid = std::min<int64_t>(static_cast<int64_t>(cus) * per_cu, std::max<int64_t>(total, 1));
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, d_counter);
+    AA_HIP(hipGetLastError());
+    hipLaunchKernelGGL(kBatchKernels[variant], dim3(static_cast<unsigned>(grid)), dim3(64 * V.waves), lds, stream,
+                       d_args, d_item_begin, nbeams, total, d_counter);
     AA_HIP(hipGetLastError());
     return AA_OK;
 }

@@ -215,7 +215,7 @@ __global__ __launch_bounds__(256) void sps_emit_kernel(
     const int32_t* __restrict__ dd, int64_t dd_pitch, int64_t dd_t0, int64_t t_begin, int32_t B,
     int32_t ndm, SpsConst sc, const double* __restrict__ norms, const int32_t* __restrict__ rowcount,
     const uint32_t* __restrict__ mask, int64_t nwords, aa_candidate_t* __restrict__ cand, int32_t cap,
-    int32_t* __restrict__ count) {
+    int32_t* __restrict__ count, int32_t beam_id) {
     __shared__ int sh[4];
     __shared__ int64_t red[4];
     const int d = blockIdx.x;
@@ -261,7 +261,7 @@ __global__ __launch_bounds__(256) void sps_emit_kernel(
                 c.width = wbest;
                 c.t = t;
                 c.snr = static_cast<float>(v);
-                c.beam = 0;
+                c.beam = beam_id;
                 cand[pos] = c;
             }
             ++pos;
@@ -296,7 +296,8 @@ size_t sps_work_bytes(const aa_plan_s* p, int64_t n_starts) { return n_starts > 
 
 int launch_single_pulse(const aa_plan_s* p, const int32_t* d_dd, int64_t dd_pitch, int64_t dd_t0, int64_t dd_n,
                         int64_t t_begin, int64_t t_end, int64_t t_total, void* d_work, aa_candidate_t* d_cand,
-                        int32_t cap, int32_t* d_count, float* d_best, int64_t best_pitch, hipStream_t stream) {
+                        int32_t cap, int32_t* d_count, float* d_best, int64_t best_pitch, hipStream_t stream,
+                        int32_t beam_id) {
     const int64_t n = t_end - t_begin;
     const WorkLayout L = layout(p, n);
     uint8_t* w = static_cast<uint8_t*>(d_work);
@@ -323,7 +324,7 @@ int launch_single_pulse(const aa_plan_s* p, const int32_t* d_dd, int64_t dd_pitc
     AA_HIP(hipGetLastError());
     hipLaunchKernelGGL(sps_emit_kernel, dim3(static_cast<unsigned>(p->ndm)), dim3(256), 0, stream, d_dd, dd_pitch,
                        dd_t0, t_begin, p->stat_block, p->ndm, sc, norms, rowcount, mask, L.nwords, d_cand, cap,
-                       d_count);
+                       d_count, beam_id);
     AA_HIP(hipGetLastError());
     return AA_OK;
 }

@@ -100,3 +100,32 @@ def batched_beams(nbeams: int = 64, seed: int = 4, nsamp_range=(1 << 16, 1 << 20
                           tsamp=64e-6, dms=dms, widths=POW2_256, threshold=6.0, stat_block=32768,
                           seed=seed * 1000 + b, pulses=pulses))
     return beams
+
+
+def serving_beams(nbeams: int = 32, seed: int = 5, ndm_range=(500, 4096), rate_range=(0.5, 2.0)) -> list:
+    """Beams of the serving workload: 4096 channels, 64 us, 2^17-sample chunks (8.39 s of
+    sky each), ndm uniform in `ndm_range` (doubling-step plan), and a Poisson arrival rate
+    of U[0.5, 2] times real time per beam."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 0x5E4F]))
+    out = []
+    for b in range(nbeams):
+        ndm = int(rng.integers(ndm_range[0], ndm_range[1] + 1))
+        out.append(dict(name=f"beam{b}", nchan=4096, f_top=1450.0, foff=300.0 / 4096, tsamp=64e-6,
+                        dms=dm_plan(ndm), widths=POW2_256, threshold=6.0, stat_block=32768,
+                        rate=float(rng.uniform(*rate_range)), chunk=1 << 17))
+    return out
+
+
+def poisson_arrivals(beams: list, duration_s: float, seed: int = 6, rate_scale: float = 1.0) -> list:
+    """Sorted (time_s, beam) arrivals. Beam b emits a chunk every chunk*tsamp/rate seconds
+    on average (exponential gaps)."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 0xA771]))
+    ev = []
+    for i, b in enumerate(beams):
+        lam = b["rate"] * rate_scale / (b["chunk"] * b["tsamp"])
+        t = float(rng.exponential(1.0 / lam))
+        while t < duration_s:
+            ev.append((t, i))
+            t += float(rng.exponential(1.0 / lam))
+    ev.sort()
+    return ev
