@@ -136,7 +136,8 @@ int aa_dedisperse(aa_plan_t plan, const uint8_t* d_in, int64_t in_pitch, int64_t
  */
 typedef struct {
     int32_t id, waves, dm_per_wave, trials_per_block, lds_bytes;
-    int32_t layout;   /* 0: a lane owns 16 contiguous samples; 1: four groups of 4, 256 apart */
+    int32_t layout;   /* 0, 3: a lane owns 16 contiguous samples; 1, 2: four groups of 4, 256 apart
+                         (2 reuses a window when the next trial has the same offset) */
 } aa_variant_t;
 
 int aa_variant_count(void);

@@ -35,9 +35,10 @@ struct DedispVariant {
     int waves;       // waves per work-group
     int dpw;         // DM trials per wave
     int lds_bytes;   // LDS budget per work-group (both buffers)
-    int layout;      // 0: lane owns 16 contiguous samples (ds_read_b128); 1: four 4-sample groups (ds_read2_b32)
+    int layout;      // 0/3: lane owns 16 contiguous samples (ds_read_b128; 4-way or 16-way switch)
+                     // 1/2: four 4-sample groups (ds_read2_b32; 2 reuses equal-offset windows)
 };
-constexpr int kNumDedispVariants = 6;
+constexpr int kNumDedispVariants = 11;
 extern const DedispVariant kDedispVariants[kNumDedispVariants];
 constexpr int kDefaultDedispVariant = 0;
 

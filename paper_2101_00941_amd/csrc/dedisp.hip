@@ -81,6 +81,43 @@ __device__ __forceinline__ void window4x4(const uint8_t* lanep, int o, uint32_t 
     }
 }
 
+// Contiguous layout, two channels at once: the register offsets QA, QB of the two
+// windows are template constants. So each case of the 16-way uniform switch below
+// perms straight from the loaded dwords into the accumulators, with no register copies.
+template <int QA, int QB>
+__device__ __forceinline__ void acc_pair16(uint32_t (&acc)[8], const u32x4& a0, const u32x4& a1, const u32x4& b0,
+                                           const u32x4& b1, uint32_t sa0, uint32_t sa1, uint32_t sb0,
+                                           uint32_t sb1) {
+    const uint32_t wa[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+    const uint32_t wb[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int ia = QA + (j >> 1), ib = QB + (j >> 1);
+        acc[j] = acc[j] + __builtin_amdgcn_perm(wa[ia + 1], wa[ia], (j & 1) ? sa1 : sa0) +
+                 __builtin_amdgcn_perm(wb[ib + 1], wb[ib], (j & 1) ? sb1 : sb0);
+    }
+    // keep the adds inside this case: without the barrier the compiler sinks the common
+    // adds below the switch and merges the perm results through register copies
+    asm volatile("" : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]), "+v"(acc[4]), "+v"(acc[5]),
+                 "+v"(acc[6]), "+v"(acc[7]));
+}
+
+#define AA_PAIR_CASE(QA, QB) \
+    case QA * 4 + QB: acc_pair16<QA, QB>(acc, a0, a1, b0, b1, sa0, sa1, sb0, sb1); break;
+
+__device__ __forceinline__ void acc_pair16_dispatch(uint32_t (&acc)[8], const u32x4& a0, const u32x4& a1,
+                                                    const u32x4& b0, const u32x4& b1, int oa, int ob) {
+    const uint32_t sa0 = 0x0C010C00u + static_cast<uint32_t>(oa & 3) * 0x00010001u, sa1 = sa0 + 0x00020002u;
+    const uint32_t sb0 = 0x0C010C00u + static_cast<uint32_t>(ob & 3) * 0x00010001u, sb1 = sb0 + 0x00020002u;
+    switch (((oa >> 2) & 3) * 4 + ((ob >> 2) & 3)) {
+        AA_PAIR_CASE(0, 0) AA_PAIR_CASE(0, 1) AA_PAIR_CASE(0, 2) AA_PAIR_CASE(0, 3)
+        AA_PAIR_CASE(1, 0) AA_PAIR_CASE(1, 1) AA_PAIR_CASE(1, 2) AA_PAIR_CASE(1, 3)
+        AA_PAIR_CASE(2, 0) AA_PAIR_CASE(2, 1) AA_PAIR_CASE(2, 2) AA_PAIR_CASE(2, 3)
+        AA_PAIR_CASE(3, 0) AA_PAIR_CASE(3, 1) AA_PAIR_CASE(3, 2) default: AA_PAIR_CASE(3, 3)
+    }
+}
+#undef AA_PAIR_CASE
+
 // One (DM block, time tile) of one beam. Used by the per-plan launch and by the
 // batched persistent launch.
 template <int DPW, int W, int LAYOUT>
@@ -152,7 +189,7 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, int blk, int64_
             since_flush = 0;
         }
         since_flush += CP;
-        const uint8_t* bufp = lds + (p & 1) * CP * row + (LAYOUT == 0 ? 16 : 4) * lane;
+        const uint8_t* bufp = lds + (p & 1) * CP * row + ((LAYOUT == 0 || LAYOUT == 3) ? 16 : 4) * lane;
         const int32_t* po = woffs + static_cast<int64_t>(p) * CP * BD;
         // offsets of the first channel pair; the next pair's are fetched one step ahead
         int oa[DPW], ob[DPW];
@@ -188,6 +225,40 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, int blk, int64_
                     uint32_t pa[8], pb[8];
                     window16(xa[i][0], xa[i][1], oa[i], pa);
                     window16(xb[i][0], xb[i][1], ob[i], pb);
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) a16[i][j] = a16[i][j] + pa[j] + pb[j];
+                }
+            } else if constexpr (LAYOUT == 3) {
+                u32x4 xa[DPW][2], xb[DPW][2];
+#pragma unroll
+                for (int i = 0; i < DPW; ++i) {
+                    const u32x4* va = reinterpret_cast<const u32x4*>(ra + (oa[i] & ~15));
+                    const u32x4* vb = reinterpret_cast<const u32x4*>(rb + (ob[i] & ~15));
+                    xa[i][0] = va[0];
+                    xa[i][1] = va[1];
+                    xb[i][0] = vb[0];
+                    xb[i][1] = vb[1];
+                }
+#pragma unroll
+                for (int i = 0; i < DPW; ++i) {
+                    na[i] = po[cn * BD + i];
+                    nb[i] = po[(cn + 1) * BD + i];
+                }
+#pragma unroll
+                for (int i = 0; i < DPW; ++i)
+                    acc_pair16_dispatch(a16[i], xa[i][0], xa[i][1], xb[i][0], xb[i][1], oa[i], ob[i]);
+            } else if constexpr (LAYOUT == 2) {
+#pragma unroll
+                for (int i = 0; i < DPW; ++i) {
+                    na[i] = po[cn * BD + i];
+                    nb[i] = po[(cn + 1) * BD + i];
+                }
+                // a trial whose window offset equals the previous trial's reuses its pairs
+                uint32_t pa[8], pb[8];
+#pragma unroll
+                for (int i = 0; i < DPW; ++i) {
+                    if (i == 0 || oa[i] != oa[i - 1]) window4x4(ra, oa[i], pa);
+                    if (i == 0 || ob[i] != ob[i - 1]) window4x4(rb, ob[i], pb);
 #pragma unroll
                     for (int j = 0; j < 8; ++j) a16[i][j] = a16[i][j] + pa[j] + pb[j];
                 }
@@ -230,7 +301,7 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, int blk, int64_
         // t0 + 256 (k >> 2) + 4 lane + (k & 3) (interleaved layout)
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
-            const int64_t t = LAYOUT == 0 ? t0 + 16 * lane + 4 * g : t0 + 256 * g + 4 * lane;
+            const int64_t t = (LAYOUT == 0 || LAYOUT == 3) ? t0 + 16 * lane + 4 * g : t0 + 256 * g + 4 * lane;
             if (t + 4 <= n_out) {
                 const u32x4 v = {a32[i][4 * g], a32[i][4 * g + 1], a32[i][4 * g + 2], a32[i][4 * g + 3]};
                 *reinterpret_cast<u32x4*>(orow + t) = v;
@@ -263,7 +334,11 @@ __global__ __launch_bounds__(64 * W) void dedisp_batch_kernel(const DedispArgs* 
     for (;;) {
         if (threadIdx.x == 0) item = static_cast<int64_t>(atomicAdd(counter, 1ull));
         __syncthreads();
-        const int64_t it = item;
+        // the item index is the same in every lane: keep it in scalar registers
+        const uint64_t itu = static_cast<uint64_t>(item);
+        const int64_t it = static_cast<int64_t>(
+            (static_cast<uint64_t>(__builtin_amdgcn_readfirstlane(static_cast<uint32_t>(itu >> 32))) << 32) |
+            static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<uint32_t>(itu))));
         __syncthreads();
         if (it >= total) break;
         int lo = 0, hi = nbeams - 1;
@@ -284,12 +359,12 @@ typedef void (*DedispFn)(DedispArgs);
 typedef void (*DedispBatchFn)(const DedispArgs*, const int64_t*, int, int64_t, unsigned long long*);
 
 // Indexed by DedispVariant::id (tiling.cpp).
-const DedispFn kKernels[kNumDedispVariants] = {
-    dedisp_kernel<4, 4, 1>, dedisp_kernel<2, 8, 1>, dedisp_kernel<4, 8, 1>, dedisp_kernel<2, 16, 1>,
-    dedisp_kernel<2, 8, 0>, dedisp_kernel<4, 4, 0>};
-const DedispBatchFn kBatchKernels[kNumDedispVariants] = {
-    dedisp_batch_kernel<4, 4, 1>, dedisp_batch_kernel<2, 8, 1>, dedisp_batch_kernel<4, 8, 1>,
-    dedisp_batch_kernel<2, 16, 1>, dedisp_batch_kernel<2, 8, 0>, dedisp_batch_kernel<4, 4, 0>};
+#define AA_VARIANTS(K)                                                                           \
+    K<4, 4, 1>, K<2, 8, 1>, K<4, 8, 1>, K<2, 16, 1>, K<2, 8, 0>, K<4, 4, 0>, K<2, 8, 3>, K<4, 4, 3>, \
+        K<2, 8, 2>, K<4, 8, 2>, K<4, 4, 2>
+const DedispFn kKernels[kNumDedispVariants] = {AA_VARIANTS(dedisp_kernel)};
+const DedispBatchFn kBatchKernels[kNumDedispVariants] = {AA_VARIANTS(dedisp_batch_kernel)};
+#undef AA_VARIANTS
 
 }  // namespace
 

@@ -15,6 +15,11 @@ const DedispVariant kDedispVariants[kNumDedispVariants] = {
     {3, 16, 2, 81920, 1},   // 1024 threads, 32 trials per block, interleaved lanes
     {4, 8, 2, 53248, 0},    // 512 threads, 16 trials per block, contiguous lanes
     {5, 4, 4, 53248, 0},    // 256 threads, 16 trials per block, contiguous lanes
+    {6, 8, 2, 53248, 3},    // 512 threads, 16 trials per block, contiguous lanes, 16-way switch
+    {7, 4, 4, 53248, 3},    // 256 threads, 16 trials per block, contiguous lanes, 16-way switch
+    {8, 8, 2, 53248, 2},    // 512 threads, 16 trials per block, interleaved, equal-offset reuse
+    {9, 8, 4, 81920, 2},    // 512 threads, 32 trials per block, interleaved, equal-offset reuse
+    {10, 4, 4, 53248, 2},   // 256 threads, 16 trials per block, interleaved, equal-offset reuse
 };
 
 void free_tables(DedispTables& t) {
