@@ -85,7 +85,36 @@ __global__ __launch_bounds__(256) void sps_stats_kernel(const int32_t* __restric
 // ---- detection ----------------------------------------------------------------
 constexpr int kHaloRows = kSpsRows + 2;
 constexpr int kHaloCols = kSpsTile + 2;
+// LDS region shared by the exact path (float64 best per halo cell) and the float32
+// screen (centres, fractions, r, best32 and its error bound)
+constexpr int kExactBytes = kHaloRows * kHaloCols * 8;
+constexpr int kScreenBytes = kHaloRows * kMaxWidths * (8 + 4 + 4) + kHaloRows * kHaloCols * (4 + 4);
+constexpr int kBestBytes = ((kExactBytes > kScreenBytes ? kExactBytes : kScreenBytes) + 15) / 16 * 16;
 
+// Exact value of one halo cell: best S/N over the widths, float64, same operation order
+// as the oracle. -inf outside the range of rows and starts.
+__device__ __forceinline__ double exact_best(const uint32_t* pre, int pw, const double* nrm, const SpsConst& sc,
+                                             int r, int c, bool valid) {
+    if (!valid) return -__builtin_huge_val();
+    const uint32_t* pr = pre + r * pw + c;
+    const double* nr = nrm + r * 2 * kMaxWidths;
+    double v = 0.0;
+    for (int k = 0; k < sc.nw; ++k) {
+        const uint32_t s = pr[sc.widths[k]] - pr[0];
+        const double snr = (static_cast<double>(s) - nr[k]) * nr[sc.nw + k];
+        if (k == 0 || snr > v) v = snr;
+    }
+    return v;
+}
+
+// EXACT: every halo cell in float64 (needed when the best plane is an output).
+// Otherwise a float32 screen runs first: boxcar sums are centred on the integer nearest
+// w*mu, and the S/N error is bounded by eps = 2^-20 (|S/N| + r + 1), well above the
+// float32 rounding of the centred value, the centre's fraction and r. Only cells with
+// best32 >= threshold - eps are evaluated exactly, together with their 8 neighbours. The
+// peak decision is then the exact float64 rule, and every other cell is certainly below
+// the threshold.
+template <bool EXACT>
 __global__ __launch_bounds__(256) void sps_detect_kernel(
     const int32_t* __restrict__ dd, int64_t dd_pitch, int64_t dd_t0, int64_t dd_n, int64_t t_begin,
     int64_t t_end, int64_t t_total, int32_t B, int32_t ndm, double threshold, SpsConst sc,
@@ -94,8 +123,8 @@ __global__ __launch_bounds__(256) void sps_detect_kernel(
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
     const int tw = kSpsTile + 1 + sc.wmax;            // D columns t_tile0-1 .. t_tile0+255+wmax
     const int pw = tw + 1;                            // prefix entries per row
-    double* best = reinterpret_cast<double*>(smem);                      // [kHaloRows][kHaloCols]
-    double* nrm = best + kHaloRows * kHaloCols;                          // [kHaloRows][2*nw]
+    double* best = reinterpret_cast<double*>(smem);                      // kBestBytes, see above
+    double* nrm = reinterpret_cast<double*>(smem + kBestBytes);          // [kHaloRows][2*nw]
     uint32_t* pre = reinterpret_cast<uint32_t*>(nrm + kHaloRows * 2 * kMaxWidths);  // [kHaloRows][pw]
     __shared__ int32_t cnt[kSpsRows];
 
@@ -147,22 +176,52 @@ __global__ __launch_bounds__(256) void sps_detect_kernel(
         }
     }
     __syncthreads();
-    // best S/N over widths for every halo cell
-    for (int i = tid; i < kHaloRows * kHaloCols; i += 256) {
-        const int r = i / kHaloCols, c = i - r * kHaloCols;
-        const int d = d0 - 1 + r;
-        const int64_t t = tt0 - 1 + c;
-        double v = -__builtin_huge_val();
-        if (d >= 0 && d < ndm && t >= lo && t < hi) {
-            const uint32_t* pr = pre + r * pw + c;      // pr[k] = sum of columns c..c+k-1
-            const double* nr = nrm + r * 2 * kMaxWidths;
-            for (int k = 0; k < sc.nw; ++k) {
-                const uint32_t s = pr[sc.widths[k]] - pr[0];
-                const double snr = (static_cast<double>(s) - nr[k]) * nr[sc.nw + k];
-                if (k == 0 || snr > v) v = snr;
-            }
+    if constexpr (EXACT) {
+        // best S/N over widths for every halo cell
+        for (int i = tid; i < kHaloRows * kHaloCols; i += 256) {
+            const int r = i / kHaloCols, c = i - r * kHaloCols;
+            const int d = d0 - 1 + r;
+            const int64_t t = tt0 - 1 + c;
+            best[i] = exact_best(pre, pw, nrm, sc, r, c, d >= 0 && d < ndm && t >= lo && t < hi);
         }
-        best[i] = v;
+    } else {
+        // float32 screen: per row and width, the integer centre c = rint(w*mu), the
+        // fraction (w*mu - c) and r as floats
+        int64_t* cen = reinterpret_cast<int64_t*>(best);                    // [kHaloRows][kMaxWidths]
+        float* frac = reinterpret_cast<float*>(cen + kHaloRows * kMaxWidths);
+        float* r32 = frac + kHaloRows * kMaxWidths;
+        float* b32 = r32 + kHaloRows * kMaxWidths;                          // [kHaloRows][kHaloCols]
+        float* e32 = b32 + kHaloRows * kHaloCols;
+        for (int i = tid; i < kHaloRows * sc.nw; i += 256) {
+            const int r = i / sc.nw, k = i - r * sc.nw;
+            const double wmu = nrm[r * 2 * kMaxWidths + k];
+            const double c = __builtin_rint(wmu);
+            cen[r * kMaxWidths + k] = static_cast<int64_t>(c);
+            frac[r * kMaxWidths + k] = static_cast<float>(wmu - c);
+            r32[r * kMaxWidths + k] = static_cast<float>(nrm[r * 2 * kMaxWidths + sc.nw + k]);
+        }
+        __syncthreads();
+        for (int i = tid; i < kHaloRows * kHaloCols; i += 256) {
+            const int r = i / kHaloCols, c = i - r * kHaloCols;
+            const int d = d0 - 1 + r;
+            const int64_t t = tt0 - 1 + c;
+            float v = -__builtin_huge_valf(), amax = 0.0f, rmax = 0.0f;
+            if (d >= 0 && d < ndm && t >= lo && t < hi) {
+                const uint32_t* pr = pre + r * pw + c;
+                for (int k = 0; k < sc.nw; ++k) {
+                    const int64_t dv = static_cast<int64_t>(pr[sc.widths[k]] - pr[0]) - cen[r * kMaxWidths + k];
+                    const float x = static_cast<float>(static_cast<int32_t>(dv >> 12)) * 4096.0f +
+                                    static_cast<float>(static_cast<int32_t>(dv & 4095));
+                    const float rr = r32[r * kMaxWidths + k];
+                    const float snr = (x - frac[r * kMaxWidths + k]) * rr;
+                    v = (k == 0 || snr > v) ? snr : v;
+                    amax = fmaxf(amax, fabsf(snr));
+                    rmax = fmaxf(rmax, rr);
+                }
+            }
+            b32[i] = v;
+            e32[i] = 9.5367431640625e-07f * (amax + rmax + 1.0f);   // 2^-20
+        }
     }
     __syncthreads();
     // 3x3 peak test for the inner rows, 64 consecutive starts per wave step
@@ -172,11 +231,30 @@ __global__ __launch_bounds__(256) void sps_detect_kernel(
         const int64_t t = tt0 + tc;
         bool ok = false;
         if (d < ndm && t < tile_end) {
-            const double* m = best + (ri + 1) * kHaloCols + (tc + 1);
-            const double v = m[0];
-            ok = v >= threshold && v > m[-kHaloCols - 1] && v > m[-kHaloCols] && v > m[-kHaloCols + 1] &&
-                 v > m[-1] && v >= m[1] && v >= m[kHaloCols - 1] && v >= m[kHaloCols] && v >= m[kHaloCols + 1];
-            if (best_out) best_out[static_cast<int64_t>(d) * best_pitch + (t - t_begin)] = static_cast<float>(v);
+            if constexpr (EXACT) {
+                const double* m = best + (ri + 1) * kHaloCols + (tc + 1);
+                const double v = m[0];
+                ok = v >= threshold && v > m[-kHaloCols - 1] && v > m[-kHaloCols] && v > m[-kHaloCols + 1] &&
+                     v > m[-1] && v >= m[1] && v >= m[kHaloCols - 1] && v >= m[kHaloCols] && v >= m[kHaloCols + 1];
+                if (best_out) best_out[static_cast<int64_t>(d) * best_pitch + (t - t_begin)] = static_cast<float>(v);
+            } else {
+                const int64_t* cen = reinterpret_cast<const int64_t*>(best);
+                const float* b32 = reinterpret_cast<const float*>(cen + kHaloRows * kMaxWidths) + 2 * kHaloRows * kMaxWidths;
+                const float* e32 = b32 + kHaloRows * kHaloCols;
+                const int ci = (ri + 1) * kHaloCols + (tc + 1);
+                if (b32[ci] >= static_cast<float>(threshold) - e32[ci]) {
+                    auto val = [&](int r, int c) {
+                        const int dr = d0 - 1 + r;
+                        const int64_t tr = tt0 - 1 + c;
+                        return exact_best(pre, pw, nrm, sc, r, c, dr >= 0 && dr < ndm && tr >= lo && tr < hi);
+                    };
+                    const int r0 = ri + 1, c0 = tc + 1;
+                    const double v = val(r0, c0);
+                    ok = v >= threshold && v > val(r0 - 1, c0 - 1) && v > val(r0 - 1, c0) && v > val(r0 - 1, c0 + 1) &&
+                         v > val(r0, c0 - 1) && v >= val(r0, c0 + 1) && v >= val(r0 + 1, c0 - 1) &&
+                         v >= val(r0 + 1, c0) && v >= val(r0 + 1, c0 + 1);
+                }
+            }
         }
         const uint64_t bal = __ballot(ok);
         if ((tid & 63) == 0 && d < ndm) {
@@ -315,10 +393,10 @@ int launch_single_pulse(const aa_plan_s* p, const int32_t* d_dd, int64_t dd_pitc
                        0, stream, d_dd, dd_pitch, dd_t0, t_begin, t_end, p->stat_block, p->ndm, sc, norms, rowcount);
     AA_HIP(hipGetLastError());
     const int tw = kSpsTile + 1 + p->wmax;
-    const size_t lds = sizeof(double) * (kHaloRows * kHaloCols + kHaloRows * 2 * kMaxWidths) +
-                       sizeof(uint32_t) * kHaloRows * (tw + 1);
+    const size_t lds = kBestBytes + sizeof(double) * (kHaloRows * 2 * kMaxWidths) + sizeof(uint32_t) * kHaloRows * (tw + 1);
     const unsigned rowblocks = static_cast<unsigned>((p->ndm + kSpsRows - 1) / kSpsRows);
-    hipLaunchKernelGGL(sps_detect_kernel, dim3(static_cast<unsigned>(L.ntiles), rowblocks), dim3(256), lds, stream,
+    hipLaunchKernelGGL(d_best ? sps_detect_kernel<true> : sps_detect_kernel<false>,
+                       dim3(static_cast<unsigned>(L.ntiles), rowblocks), dim3(256), lds, stream,
                        d_dd, dd_pitch, dd_t0, dd_n, t_begin, t_end, t_total, p->stat_block, p->ndm,
                        static_cast<double>(p->threshold), sc, norms, rowcount, mask, L.nwords, d_best, best_pitch);
     AA_HIP(hipGetLastError());

@@ -110,18 +110,39 @@ def _signal(nchan=32, nsamp=40000, seed=8):
 
 
 @pytest.mark.parametrize("widths", [[1, 2, 4, 8, 16], [1, 3, 10, 50], [7]])
-def test_multiblock_candidates(widths):
+@pytest.mark.parametrize("with_best", [True, False])   # exact path / float32-screened path
+def test_multiblock_candidates(widths, with_best):
     nchan, nsamp = 32, 40000
     x = _signal(nchan, nsamp)
     dms = np.arange(0, 60, 1.0)
-    say(f"multiblock widths {widths}")
+    say(f"multiblock widths {widths} best plane {with_best}")
     want = oracle.run(x, nsamp, 1500.0, 1.5, 64e-6, dms, widths, 5.0, stat_block=4096, want_best=True)
     p = _plan(nchan, nsamp, 1500.0, 1.5, 64e-6, dms, widths, 5.0, 4096)
-    r = run_gpu(p, x, nsamp)
+    r = run_gpu(p, x, nsamp, want_best=with_best)
     assert np.array_equal(r["D"], want["D"])
     assert len(want["candidates"]) > 3
     assert_candidates_equal(r["candidates"], want["candidates"])
-    assert np.array_equal(r["best"], want["best"])
+    if with_best:
+        assert np.array_equal(r["best"], want["best"])
+
+
+def test_screened_path_on_tiny_workload(tiny, tiny_oracle):
+    from paper_2101_00941_amd import Plan
+    w, x = tiny
+    r = run_gpu(Plan.from_workload(w), x, w["nsamp"], want_best=False)
+    assert_candidates_equal(r["candidates"], tiny_oracle["candidates"])
+
+
+@pytest.mark.parametrize("thr", [0.0, 3.0, 25.0])
+def test_screened_path_thresholds(thr):
+    # low thresholds make most cells "hot" (exact path everywhere); high ones make nearly none
+    nchan, nsamp = 32, 20000
+    x = _signal(nchan, 40000)[:, :nsamp].copy()
+    dms = np.arange(0, 40, 1.0)
+    want = oracle.run(x, nsamp, 1500.0, 1.5, 64e-6, dms, [1, 2, 4], thr, stat_block=4096)
+    p = _plan(nchan, nsamp, 1500.0, 1.5, 64e-6, dms, [1, 2, 4], thr, 4096)
+    r = run_gpu(p, x, nsamp, want_best=False, cap=1 << 18)
+    assert_candidates_equal(r["candidates"], want["candidates"])
 
 
 def test_subrange_call_matches_oracle():
