@@ -36,13 +36,13 @@ def beams():
 
 
 @pytest.mark.parametrize("static", [False, True])
-@pytest.mark.parametrize("work_mb", [512, 24])          # 24 MB forces several groups
+@pytest.mark.parametrize("work_mb", [512, 40])          # 40 MB forces several groups
 def test_batch_equals_plain_per_beam(beams, static, work_mb):
     from paper_2101_00941_amd import batch_run, candidates_as_tuples
     say(f"batch static={static} work={work_mb} MB")
     cands, counts, info = batch_run([(b["plan"], b["dev"], b["nsamp"]) for b in beams], variant=1,
                                     work_bytes=work_mb << 20, cap=4096, static=static)
-    if work_mb == 24:
+    if work_mb == 40:
         assert info["groups"] > 1
     for i, b in enumerate(beams):
         plain = run_gpu(b["plan"], b["x"], b["nsamp"], cap=4096, want_best=False)
