@@ -37,8 +37,34 @@ struct DedispVariant {
     int lds_bytes;   // LDS budget per work-group (both buffers)
     int layout;      // 0/3: lane owns 16 contiguous samples (ds_read_b128; 4-way or 16-way switch)
                      // 1/2: four 4-sample groups (ds_read2_b32; 2 reuses equal-offset windows)
+                     // 4: matrix-core contraction (v_mfma_i32_32x32x32_i8), see below
 };
-constexpr int kNumDedispVariants = 11;
+constexpr int kNumDedispVariants = 12;
+
+// Matrix-core variant (layout 4). Within a block of up to 32 trials (first trial d0)
+// and a run of channels, the shift splits exactly as
+//   s[d][c] = base[c] + E[d] + r[d][c],  base[c] = s[d0][c],  0 <= r < 8.
+// For rows t' of a shifted time axis, the partial sum over the run,
+//   P[t'][d] = sum_c X[c][t' + base[c] + r[d][c]],
+// is a product of the matrix A[t'][(c, r)] = X[c][t' + base[c] + r] with the one-hot
+// matrix B[(c, r)][d] = (r == r[d][c]). D[d][t] receives P[t + E[d]][d]. One
+// MFMA step contracts 4 channels x 8 residuals. A channel block ends where the
+// residual range of the next 4 channels would reach 8.
+constexpr int kMfmaWaves = 8;           // 512 threads
+constexpr int kMfmaTilesPerWave = 8;    // 32-row tiles of t' per wave
+constexpr int kMfmaMaxTiles = 63;       // rows of t' per channel block <= 63 * 32
+constexpr int kMfmaRow = 2048;          // staged bytes per channel row
+constexpr int kMfmaRec = 256;           // per-step table record (bytes)
+constexpr int kMfmaAccBytes = kTimeTile * 32 * 4;                          // int32 [1024][32]
+constexpr int kMfmaLds = kMfmaAccBytes + 3 * 4 * kMfmaRow + 3 * kMfmaRec;  // 3-deep staging ring
+// Record layout (one per DM block and 4-channel step k):
+//   [0, 128)    u8  8*r[d][4k+i] at 4d+i (d < 32, i < 4)
+//   [128, 192)  i16 e[d] = E[d] - min E of the channel block holding step k
+//   [192, 196)  u8  phase of the 4 staged rows (their start mod 16)
+//   [196, 200)  i32 rows of t' in 32-row tiles for that channel block
+//   [200, 204)  i32 1 if the channel block ends with step k
+//   [204, 220)  i32 16-aligned row starts (relative to the time tile) of step k + 2
+constexpr int kRecE = 128, kRecPhase = 192, kRecTiles = 196, kRecEnd = 200, kRecNextRs = 204;
 extern const DedispVariant kDedispVariants[kNumDedispVariants];
 constexpr int kDefaultDedispVariant = 0;
 
@@ -66,6 +92,7 @@ struct DedispTables {
     DmBlock* d_blocks = nullptr;
     int32_t* d_base = nullptr;
     int32_t* d_offs = nullptr;
+    uint8_t* d_pad = nullptr;        // layout 4: one staged row of 0x80 bytes (padded channels)
 };
 
 // Arguments of one dedispersion launch (one beam), passed by value or from a device table.
@@ -78,6 +105,7 @@ struct DedispArgs {
     int32_t nblk, nchan, nchan_pad, row;
     int32_t* out;
     int64_t out_pitch, n_out, ntile;
+    const uint8_t* pad;
 };
 
 }  // namespace aa
@@ -104,6 +132,10 @@ struct aa_plan_s {
 namespace aa {
 // Builds (host) and uploads (device, unless the plan is host-only) the tables of a variant.
 int prepare_variant(aa_plan_s* p, int variant);
+// Host tables of the matrix-core variant: DM blocks, 16-aligned staged-row starts
+// [nblk][nchan4] and the per-step records [nblk][nchan4 / 4][kMfmaRec].
+int build_mfma_tables(const aa_plan_s* p, std::vector<DmBlock>& blocks, std::vector<int32_t>& rsv,
+                      std::vector<uint8_t>& rec);
 void free_tables(DedispTables& t);
 // Launchers (dedisp.hip, sps.hip). Arguments are validated by the callers.
 int launch_dedisperse(const aa_plan_s* p, int variant, const uint8_t* d_in, int64_t in_pitch, int64_t n_in,

@@ -314,10 +314,209 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, int blk, int64_
     }
 }
 
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+typedef int32_t i32x16 __attribute__((ext_vector_type(16)));
+
+// The tiles of one step. Wave w owns tiles w + 8 j; a channel block has at least 32
+// tiles, so tiles j < 4 always exist and tiles 4..7 exist for j < nt. All LDS windows
+// are read first, then aligned, re-biased (x - 128) and contracted.
+__device__ __forceinline__ void mfma_step(i32x16 (&acc)[kMfmaTilesPerWave], const uint8_t* lds, int w0, int w1,
+                                          uint32_t u0, uint32_t u1, const i32x4& B, int nt) {
+    uint32_t x[8][3], y[8][3];
+    auto load = [&](int j) {
+        // tiles 4..7 use the base + 1024 so that ds_read2 offsets stay within 8 bits
+        const uint32_t* p0 = reinterpret_cast<const uint32_t*>(lds + w0 + 256 * j);
+        const uint32_t* p1 = reinterpret_cast<const uint32_t*>(lds + w1 + 256 * j);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            x[j][i] = p0[i];
+            y[j][i] = p1[i];
+        }
+    };
+    auto mma = [&](int j) {
+        const i32x4 Av = {static_cast<int32_t>(__builtin_amdgcn_alignbyte(x[j][1], x[j][0], u0) ^ 0x80808080u),
+                          static_cast<int32_t>(__builtin_amdgcn_alignbyte(x[j][2], x[j][1], u0) ^ 0x80808080u),
+                          static_cast<int32_t>(__builtin_amdgcn_alignbyte(y[j][1], y[j][0], u1) ^ 0x80808080u),
+                          static_cast<int32_t>(__builtin_amdgcn_alignbyte(y[j][2], y[j][1], u1) ^ 0x80808080u)};
+        acc[j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(Av, B, acc[j], 0, 0, 0);
+    };
+#pragma unroll
+    for (int j = 0; j < 4; ++j) load(j);
+#pragma unroll
+    for (int j = 4; j < 8; ++j)
+        if (j < nt) load(j);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) mma(j);
+#pragma unroll
+    for (int j = 4; j < 8; ++j)
+        if (j < nt) mma(j);
+}
+
+// Matrix-core dedispersion of one (DM block, time tile), layout 4. The shift of a
+// trial d of the block at channel c is s = base[c] + E[d] + r[d][c], with 0 <= r < 8
+// inside a channel block (the tables are built on the host, tiling.cpp). So
+//   D[d][t] = sum over channel blocks of P[t + e[d]][d],
+//   P[t'][d] = sum_{c in block} X[c][t' + base[c] + min E + r[d][c]],
+// where t' runs over a shifted time axis and e[d] = E[d] - min E. P is a product of
+// the data matrix A[t'][(c, r)] (a sliding 8-byte window per channel) and the one-hot
+// matrix B[(c, r)][d], computed exactly by v_mfma_i32_32x32x32_i8: rows are 32 values
+// of t', columns the 32 trials, and one step contracts 4 channels x 8 residuals.
+// Input bytes enter as x - 128 (signed 8-bit), and 128 * nchan is added back at the end.
+//  * 8 waves. Wave w owns the tiles w + 8 j (j < 8) of 32 rows of t' (a channel block
+//    needs 32 to 63 tiles) and holds their 32 x 32 int32 accumulators in registers.
+//  * At the end of a channel block, each accumulator row t' of trial d is added into
+//    the work-group's [1024][32] int32 tile in LDS at t = t' - e[d] (ds_add_u32). Lanes
+//    hold 32 distinct trials of one row, so these adds are conflict-free.
+//  * Input rows are staged 4 channels per step, 2048 bytes each, by direct
+//    global->LDS loads into a 3-deep ring, issued 2 steps ahead. Each step's table record
+//    (residuals, e, phases, tile count, row starts of step + 2) rides along in the
+//    same ring. Every wave issues exactly one data load per step, and wave 0 also the
+//    record, so "s_waitcnt vmcnt(1)" (wave 0: vmcnt(2)) before the step's barrier
+//    leaves only the newest step in flight.
+//  * A lane (row m, half h) reads its two channels' windows as 3 aligned dwords each
+//    and aligns them with v_alignbyte_b32. Every staged chunk that a needed byte lives
+//    in is in range; chunks wholly outside [0, n_in16) are clamped to a valid address,
+//    and their bytes only reach rows that are never written out.
+__device__ __forceinline__ void dedisp_mfma_tile(const DedispArgs& A, int blk, int64_t t0) {
+    constexpr int W = kMfmaWaves, TPW = kMfmaTilesPerWave;
+    constexpr int STAGE = 4 * kMfmaRow;
+    constexpr int RING = kMfmaAccBytes;                 // byte offsets into LDS
+    constexpr int RECS = kMfmaAccBytes + 3 * STAGE;
+    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+    int32_t* acc_lds = reinterpret_cast<int32_t*>(lds);
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63, m = lane & 31, h = lane >> 5;
+    const int K4 = A.nchan_pad >> 2;
+    const uint8_t* recg = reinterpret_cast<const uint8_t*>(A.offs) + static_cast<int64_t>(blk) * K4 * kMfmaRec;
+    const int32_t* rsv = A.base + static_cast<int64_t>(blk) * A.nchan_pad;
+    const int64_t last16 = A.n_in16 - 16;
+
+    // Loads of step k into ring slot `slot`: each wave stages half a channel row
+    // (16 bytes per lane), and wave 0 then the step's table record (4 bytes per lane).
+    static_assert(W == 8, "one wave per half row");
+    auto issue = [&](int k, int slot, int rs) {
+        {
+            const int row = wave >> 1, half = wave & 1;
+            const int c = 4 * k + row;
+            const int v = 64 * half + lane;
+            const uint8_t* src;
+            if (c < A.nchan) {
+                int64_t pos = t0 + rs + 16 * v;
+                pos = pos < 0 ? 0 : (pos > last16 ? last16 : pos);
+                src = A.in + static_cast<int64_t>(c) * A.in_pitch + pos;
+            } else {
+                src = A.pad + 16 * v;
+            }
+            __builtin_amdgcn_global_load_lds(src, (lds_void*)(lds + RING + slot * STAGE + row * kMfmaRow + half * 1024),
+                                             16, 0, 0);
+        }
+        if (wave == 0) {
+            __builtin_amdgcn_global_load_lds(recg + static_cast<int64_t>(k) * kMfmaRec + 4 * lane,
+                                             (lds_void*)(lds + RECS + slot * kMfmaRec), 4, 0, 0);
+        }
+    };
+
+    for (int i = tid; i < kMfmaAccBytes / 16; i += 64 * W) reinterpret_cast<u32x4*>(lds)[i] = u32x4{0u, 0u, 0u, 0u};
+    const int rs0 = __builtin_amdgcn_readfirstlane(rsv[wave >> 1]);
+    const int rs1 = K4 > 1 ? __builtin_amdgcn_readfirstlane(rsv[4 + (wave >> 1)]) : 0;
+    issue(0, 0, rs0);
+    if (K4 > 1) issue(1, 1, rs1);
+
+    i32x16 acc[TPW];
+#pragma unroll
+    for (int j = 0; j < TPW; ++j) acc[j] = i32x16{};
+    int slot = 0;
+    for (int k = 0; k < K4; ++k) {
+        if (k + 1 >= K4)
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        else if (wave == 0)
+            asm volatile("s_waitcnt vmcnt(2)" ::: "memory");
+        else
+            asm volatile("s_waitcnt vmcnt(1)" ::: "memory");
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        const int rec = RECS + slot * kMfmaRec;
+        auto issue_ahead = [&]() {
+            const int rs = __builtin_amdgcn_readfirstlane(
+                *reinterpret_cast<const int32_t*>(lds + rec + kRecNextRs + 4 * (wave >> 1)));
+            issue(k + 2, slot == 0 ? 2 : slot - 1, rs);
+        };
+        // one-hot B: lane (trial m, half h) holds channels 2h, 2h+1 of the step
+        const uint32_t r32 = *reinterpret_cast<const uint32_t*>(lds + rec + 4 * m);
+        const uint32_t sh0 = (r32 >> (16 * h)) & 0xFFu, sh1 = (r32 >> (16 * h + 8)) & 0xFFu;
+        const uint64_t o0 = 1ull << sh0, o1 = 1ull << sh1;
+        const i32x4 B = {static_cast<int32_t>(o0), static_cast<int32_t>(o0 >> 32), static_cast<int32_t>(o1),
+                         static_cast<int32_t>(o1 >> 32)};
+        const int nr = __builtin_amdgcn_readfirstlane(*reinterpret_cast<const int32_t*>(lds + rec + kRecTiles));
+        const int endf = __builtin_amdgcn_readfirstlane(*reinterpret_cast<const int32_t*>(lds + rec + kRecEnd));
+        const uint32_t ph = *reinterpret_cast<const uint16_t*>(lds + rec + kRecPhase + 2 * h);
+        // A flush (LDS adds) waits for every load in flight, so a step that ends a
+        // channel block issues its loads after the flush.
+        if (k + 2 < K4 && !endf) issue_ahead();
+        // data A: lane (row m, half h) reads 8-byte windows of channels 2h, 2h+1;
+        // tile j of this wave starts at row 32 (wave + 8 j)
+        const int base = RING + slot * STAGE + 2 * h * kMfmaRow + 32 * wave + m;
+        const int a0 = base + static_cast<int>(ph & 0xFFu), a1 = base + kMfmaRow + static_cast<int>(ph >> 8);
+        const int w0 = a0 & ~3, w1 = a1 & ~3;
+        const uint32_t u0 = static_cast<uint32_t>(a0 & 3), u1 = static_cast<uint32_t>(a1 & 3);
+        static_assert(TPW == 8 && W == 8, "tile ownership below");
+        mfma_step(acc, lds, w0, w1, u0, u1, B, (nr - wave + 7) >> 3);
+        if (endf) {
+            // accumulator register i of lane (m, h) holds row 8 (i / 4) + 4 h + i % 4 of
+            // the tile and trial m
+            const int e = *reinterpret_cast<const int16_t*>(lds + rec + kRecE + 2 * m);
+#pragma unroll
+            for (int j = 0; j < TPW; ++j) {
+                const int q = wave + 8 * j;
+                if (q < nr) {
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        const int t = 32 * q + 8 * (i >> 2) + 4 * h + (i & 3) - e;
+                        if (static_cast<unsigned>(t) < static_cast<unsigned>(kTimeTile))
+                            __hip_atomic_fetch_add(acc_lds + 32 * t + m, acc[j][i], __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                }
+                acc[j] = i32x16{};
+            }
+            if (k + 2 < K4) issue_ahead();
+        }
+        slot = slot == 2 ? 0 : slot + 1;
+    }
+    __syncthreads();
+
+    const DmBlock b = A.blocks[blk];
+    const int32_t corr = 128 * A.nchan;
+#pragma unroll 1
+    for (int it = 0; it < kTimeTile * 32 / 4 / (64 * W); ++it) {
+        const int idx = tid + 64 * W * it;
+        const int d = idx & 31, tq = idx >> 5;
+        int32_t v[4];
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) v[jj] = acc_lds[(4 * tq + jj) * 32 + d] + corr;
+        if (d < b.count) {
+            int32_t* orow = A.out + static_cast<int64_t>(b.first + d) * A.out_pitch;
+            const int64_t t = t0 + 4 * tq;
+            if (t + 4 <= A.n_out) {
+                *reinterpret_cast<u32x4*>(orow + t) = u32x4{static_cast<uint32_t>(v[0]), static_cast<uint32_t>(v[1]),
+                                                           static_cast<uint32_t>(v[2]), static_cast<uint32_t>(v[3])};
+            } else {
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj)
+                    if (t + jj < A.n_out) orow[t + jj] = v[jj];
+            }
+        }
+    }
+}
+
 template <int DPW, int W, int LAYOUT>
 __global__ __launch_bounds__(64 * W) void dedisp_kernel(DedispArgs a) {
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
-    dedisp_tile<DPW, W, LAYOUT>(a, bid % a.nblk, static_cast<int64_t>(bid / a.nblk) * kTimeTile);
+    if constexpr (LAYOUT == 4)
+        dedisp_mfma_tile(a, bid % a.nblk, static_cast<int64_t>(bid / a.nblk) * kTimeTile);
+    else
+        dedisp_tile<DPW, W, LAYOUT>(a, bid % a.nblk, static_cast<int64_t>(bid / a.nblk) * kTimeTile);
 }
 
 // Batched persistent launch: a grid of resident work-groups pulls (beam, DM block,
@@ -348,7 +547,10 @@ __global__ __launch_bounds__(64 * W) void dedisp_batch_kernel(const DedispArgs* 
         }
         const DedispArgs a = args[lo];
         const int64_t local = it - item_begin[lo];
-        dedisp_tile<DPW, W, LAYOUT>(a, static_cast<int>(local % a.nblk), (local / a.nblk) * kTimeTile);
+        if constexpr (LAYOUT == 4)
+            dedisp_mfma_tile(a, static_cast<int>(local % a.nblk), (local / a.nblk) * kTimeTile);
+        else
+            dedisp_tile<DPW, W, LAYOUT>(a, static_cast<int>(local % a.nblk), (local / a.nblk) * kTimeTile);
         __syncthreads();   // the next item restages LDS buffer 0
     }
 }
@@ -361,7 +563,7 @@ typedef void (*DedispBatchFn)(const DedispArgs*, const int64_t*, int, int64_t, u
 // Indexed by DedispVariant::id (tiling.cpp).
 #define AA_VARIANTS(K)                                                                           \
     K<4, 4, 1>, K<2, 8, 1>, K<4, 8, 1>, K<2, 16, 1>, K<2, 8, 0>, K<4, 4, 0>, K<2, 8, 3>, K<4, 4, 3>, \
-        K<2, 8, 2>, K<4, 8, 2>, K<4, 4, 2>
+        K<2, 8, 2>, K<4, 8, 2>, K<4, 4, 2>, K<4, 8, 4>
 const DedispFn kKernels[kNumDedispVariants] = {AA_VARIANTS(dedisp_kernel)};
 const DedispBatchFn kBatchKernels[kNumDedispVariants] = {AA_VARIANTS(dedisp_batch_kernel)};
 #undef AA_VARIANTS
@@ -389,6 +591,7 @@ DedispArgs dedisp_args(const aa_plan_s* p, int variant, const uint8_t* d_in, int
     a.n_out = n_in - p->maxshift;
     a.row = T.max_row;
     a.ntile = (a.n_out + kTimeTile - 1) / kTimeTile;
+    a.pad = T.d_pad;
     return a;
 }
 
@@ -400,7 +603,7 @@ int launch_dedisperse(const aa_plan_s* p, int variant, const uint8_t* d_in, int6
     const DedispArgs a = dedisp_args(p, variant, d_in, in_pitch, n_in, d_out, out_pitch);
     const int64_t grid = a.ntile * a.nblk;
     if (grid > 0x7fffffff) return fail(AA_EINVAL, "aa_dedisperse: too many tiles for one launch");
-    const size_t lds = static_cast<size_t>(2 * kChanPerPass) * T.max_row;
+    const size_t lds = V.layout == 4 ? static_cast<size_t>(kMfmaLds) : static_cast<size_t>(2 * kChanPerPass) * T.max_row;
     hipLaunchKernelGGL(kKernels[variant], dim3(static_cast<unsigned>(grid)), dim3(64 * V.waves), lds, stream, a);
     AA_HIP(hipGetLastError());
     return AA_OK;
@@ -409,7 +612,7 @@ int launch_dedisperse(const aa_plan_s* p, int variant, const uint8_t* d_in, int6
 int launch_dedisperse_batch(int variant, const DedispArgs* d_args, const int64_t* d_item_begin, int nbeams,
                             int64_t total, unsigned long long* d_counter, int max_row, hipStream_t stream) {
     const DedispVariant& V = kDedispVariants[variant];
-    const size_t lds = static_cast<size_t>(2 * kChanPerPass) * max_row;
+    const size_t lds = V.layout == 4 ? static_cast<size_t>(kMfmaLds) : static_cast<size_t>(2 * kChanPerPass) * max_row;
     int dev = 0, cus = 0, per_cu = 0;
     AA_HIP(hipGetDevice(&dev));
     AA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));

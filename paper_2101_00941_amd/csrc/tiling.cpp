@@ -1,6 +1,8 @@
 // Dedispersion tiling tables. Built on the host and uploaded once, at plan time or
 // when the tuner prepares a variant. Nothing here runs in the hot loop.
 #include <algorithm>
+#include <climits>
+#include <cstring>
 
 #include "aa_internal.h"
 
@@ -20,12 +22,14 @@ const DedispVariant kDedispVariants[kNumDedispVariants] = {
     {8, 8, 2, 53248, 2},    // 512 threads, 16 trials per block, interleaved, equal-offset reuse
     {9, 8, 4, 81920, 2},    // 512 threads, 32 trials per block, interleaved, equal-offset reuse
     {10, 4, 4, 53248, 2},   // 256 threads, 16 trials per block, interleaved, equal-offset reuse
+    {11, kMfmaWaves, 4, kMfmaLds, 4},   // 512 threads, 32 trials per block, i8 matrix cores
 };
 
 void free_tables(DedispTables& t) {
     if (t.d_blocks) (void)hipFree(t.d_blocks);
     if (t.d_base) (void)hipFree(t.d_base);
     if (t.d_offs) (void)hipFree(t.d_offs);
+    if (t.d_pad) (void)hipFree(t.d_pad);
     t = DedispTables();
 }
 
@@ -38,11 +42,164 @@ int upload(T** dst, const std::vector<T>& src) {
 }
 }  // namespace
 
+// Tables of the matrix-core variant (layout 4). f(d, c) = s[d][c] - s[d0][c].
+//  * DM blocks: up to 32 consecutive trials such that every 4-channel step on its own
+//    has a residual range below 8 (so a channel block always holds at least one step)
+//    and, for every channel, the spread of f over the block's trials is at most
+//    (kMfmaMaxTiles * 32 - kTimeTile). The spread of E over a channel block is bounded
+//    by that, so a channel block never needs more than kMfmaMaxTiles tiles of t'.
+//    A single trial always qualifies (f = 0).
+//  * Channel blocks: greedy runs of 4-channel steps whose residual range stays below 8.
+//    E[d] = min over the run of f(d, c), r = f - E, e = E - min E, and the staged row
+//    of channel c starts at s[d0][c] + min E (16-aligned start + phase).
+//  * Padded channels (c >= nchan) are staged from a row of 0x80 bytes, which the kernel
+//    maps to 0, so their residuals are 0. Absent trials of a short block have r = 0,
+//    e = 0 and are not written out.
+int build_mfma_tables(const aa_plan_s* p, std::vector<DmBlock>& blocks, std::vector<int32_t>& rsv,
+                      std::vector<uint8_t>& rec) {
+    const int nchan = p->nchan;
+    const int nchan4 = (nchan + 3) & ~3;
+    const int K4 = nchan4 / 4;
+    const int spread_max = kMfmaMaxTiles * 32 - kTimeTile;
+    auto S = [&](int d, int c) { return p->shifts[static_cast<size_t>(d) * nchan + c]; };
+    blocks.clear();
+    std::vector<int32_t> fmin(nchan), fmax(nchan);
+    for (int d0 = 0; d0 < p->ndm;) {
+        std::fill(fmin.begin(), fmin.end(), 0);
+        std::fill(fmax.begin(), fmax.end(), 0);
+        int count = 1;
+        while (count < 32 && d0 + count < p->ndm) {
+            const int d = d0 + count;
+            bool ok = true;
+            for (int c0 = 0; c0 < nchan && ok; c0 += 4) {
+                int lo = INT32_MAX, hi = INT32_MIN;
+                for (int c = c0; c < std::min(c0 + 4, nchan); ++c) {
+                    const int32_t f = S(d, c) - S(d0, c);
+                    lo = std::min(lo, f);
+                    hi = std::max(hi, f);
+                    if (std::max(fmax[c], f) - std::min(fmin[c], f) > spread_max) ok = false;
+                }
+                if (hi - lo > 7) ok = false;
+            }
+            if (!ok) break;
+            for (int c = 0; c < nchan; ++c) {
+                const int32_t f = S(d, c) - S(d0, c);
+                fmin[c] = std::min(fmin[c], f);
+                fmax[c] = std::max(fmax[c], f);
+            }
+            ++count;
+        }
+        blocks.push_back(DmBlock{d0, count, 0, 0});
+        d0 += count;
+    }
+    const size_t nblk = blocks.size();
+    rsv.assign(nblk * nchan4, 0);
+    rec.assign(nblk * K4 * kMfmaRec, 0);
+    std::vector<int32_t> lo(32), hi(32);
+    for (size_t bi = 0; bi < nblk; ++bi) {
+        const int d0 = blocks[bi].first, count = blocks[bi].count;
+        uint8_t* R = &rec[bi * K4 * kMfmaRec];
+        for (int k0 = 0; k0 < K4;) {
+            // grow the channel block [k0, k1) step by step
+            std::fill(lo.begin(), lo.end(), INT32_MAX);
+            std::fill(hi.begin(), hi.end(), INT32_MIN);
+            int k1 = k0;
+            while (k1 < K4) {
+                bool ok = true;
+                for (int i = 0; i < count && ok; ++i) {
+                    int l = lo[i], h = hi[i];
+                    for (int c = 4 * k1; c < std::min(4 * k1 + 4, nchan); ++c) {
+                        const int32_t f = S(d0 + i, c) - S(d0, c);
+                        l = std::min(l, f);
+                        h = std::max(h, f);
+                    }
+                    if (h - l > 7) ok = false;
+                }
+                if (!ok) break;
+                for (int i = 0; i < count; ++i)
+                    for (int c = 4 * k1; c < std::min(4 * k1 + 4, nchan); ++c) {
+                        const int32_t f = S(d0 + i, c) - S(d0, c);
+                        lo[i] = std::min(lo[i], f);
+                        hi[i] = std::max(hi[i], f);
+                    }
+                ++k1;
+            }
+            if (k1 == k0) return fail(AA_EINVAL, "matrix-core tiling: a 4-channel step exceeds the residual range");
+            int32_t emin = INT32_MAX, emax = INT32_MIN;
+            for (int i = 0; i < count; ++i) {
+                emin = std::min(emin, lo[i]);
+                emax = std::max(emax, lo[i]);
+            }
+            const int tiles = (emax - emin + kTimeTile + 31) / 32;
+            if (tiles > kMfmaMaxTiles) return fail(AA_EINVAL, "matrix-core tiling: channel block spread too large");
+            for (int k = k0; k < k1; ++k) {
+                uint8_t* rk = R + static_cast<size_t>(k) * kMfmaRec;
+                for (int j = 0; j < 4; ++j) {
+                    const int c = 4 * k + j;
+                    const int32_t v = c < nchan ? S(d0, c) + emin : 0;
+                    rsv[bi * nchan4 + c] = v & ~15;
+                    rk[kRecPhase + j] = static_cast<uint8_t>(v & 15);
+                    for (int i = 0; i < count && c < nchan; ++i) {
+                        const int32_t r = S(d0 + i, c) - S(d0, c) - lo[i];
+                        rk[4 * i + j] = static_cast<uint8_t>(8 * r);
+                    }
+                }
+                for (int i = 0; i < count; ++i) {
+                    const int16_t e = static_cast<int16_t>(lo[i] - emin);
+                    std::memcpy(rk + kRecE + 2 * i, &e, 2);
+                }
+                const int32_t end = k + 1 == k1 ? 1 : 0;
+                std::memcpy(rk + kRecTiles, &tiles, 4);
+                std::memcpy(rk + kRecEnd, &end, 4);
+            }
+            k0 = k1;
+        }
+        // row starts of step k + 2, read by the kernel when it issues that step's loads
+        for (int k = 0; k + 2 < K4; ++k)
+            std::memcpy(R + static_cast<size_t>(k) * kMfmaRec + kRecNextRs, &rsv[bi * nchan4 + 4 * (k + 2)], 16);
+    }
+    return AA_OK;
+}
+
+namespace {
+int prepare_mfma(const aa_plan_s* p, DedispTables& t) {
+    std::vector<DmBlock> blocks;
+    std::vector<int32_t> rsv;
+    std::vector<uint8_t> rec;
+    const int rc0 = build_mfma_tables(p, blocks, rsv, rec);
+    if (rc0 != AA_OK) return rc0;
+    t.bd = 32;
+    t.nchan_pad = (p->nchan + 3) & ~3;
+    t.max_row = kMfmaRow;
+    t.blocks = blocks;
+    if (p->device >= 0) {
+        std::vector<uint8_t> pad(kMfmaRow, 0x80);
+        int rc = upload(&t.d_blocks, blocks);
+        if (rc == AA_OK) rc = upload(&t.d_base, rsv);
+        if (rc == AA_OK) rc = upload(reinterpret_cast<uint8_t**>(&t.d_offs), rec);
+        if (rc == AA_OK) rc = upload(&t.d_pad, pad);
+        if (rc != AA_OK) return rc;
+    }
+    return AA_OK;
+}
+}  // namespace
+
 int prepare_variant(aa_plan_s* p, int v) {
     if (v < 0 || v >= kNumDedispVariants) return fail(AA_EINVAL, "unknown dedispersion variant");
     DedispTables& T = p->tables[v];
     if (T.variant == v) return AA_OK;
     const DedispVariant& V = kDedispVariants[v];
+    if (V.layout == 4) {
+        DedispTables t;
+        t.variant = v;
+        const int rc = prepare_mfma(p, t);
+        if (rc != AA_OK) {
+            free_tables(t);
+            return rc;
+        }
+        T = t;
+        return AA_OK;
+    }
     const int bd = V.waves * V.dpw;
     const int row_max = (V.lds_bytes / (2 * kChanPerPass)) & ~15;
     const int nchan = p->nchan;
