@@ -137,7 +137,10 @@ int aa_dedisperse(aa_plan_t plan, const uint8_t* d_in, int64_t in_pitch, int64_t
 typedef struct {
     int32_t id, waves, dm_per_wave, trials_per_block, lds_bytes;
     int32_t layout;   /* 0, 3: a lane owns 16 contiguous samples; 1, 2: four groups of 4, 256 apart
-                         (2 reuses a window when the next trial has the same offset) */
+                         (2 reuses a window when the next trial has the same offset);
+                         4: i8 matrix-core contraction over an exact split of the shift table */
+    int32_t time_tile;   /* output samples per work-group */
+    int32_t depth;       /* staging buffers per work-group (loads run depth - 1 passes ahead) */
 } aa_variant_t;
 
 int aa_variant_count(void);

@@ -38,8 +38,10 @@ struct DedispVariant {
     int layout;      // 0/3: lane owns 16 contiguous samples (ds_read_b128; 4-way or 16-way switch)
                      // 1/2: four 4-sample groups (ds_read2_b32; 2 reuses equal-offset windows)
                      // 4: matrix-core contraction (v_mfma_i32_32x32x32_i8), see below
+    int tile;        // output samples per work-group (time tile)
+    int depth;       // staging buffers in the LDS ring (loads run depth - 1 steps ahead)
 };
-constexpr int kNumDedispVariants = 12;
+constexpr int kNumDedispVariants = 14;
 
 // Matrix-core variant (layout 4). Within a block of up to 32 trials (first trial d0)
 // and a run of channels, the shift splits exactly as
@@ -50,21 +52,22 @@ constexpr int kNumDedispVariants = 12;
 // matrix B[(c, r)][d] = (r == r[d][c]). D[d][t] receives P[t + E[d]][d]. One
 // MFMA step contracts 4 channels x 8 residuals. A channel block ends where the
 // residual range of the next 4 channels would reach 8.
-constexpr int kMfmaWaves = 8;           // 512 threads
-constexpr int kMfmaTilesPerWave = 8;    // 32-row tiles of t' per wave
 constexpr int kMfmaMaxTiles = 63;       // rows of t' per channel block <= 63 * 32
 constexpr int kMfmaRow = 2048;          // staged bytes per channel row
 constexpr int kMfmaRec = 256;           // per-step table record (bytes)
-constexpr int kMfmaAccBytes = kTimeTile * 32 * 4;                          // int32 [1024][32]
-constexpr int kMfmaLds = kMfmaAccBytes + 3 * 4 * kMfmaRow + 3 * kMfmaRec;  // 3-deep staging ring
-// Record layout (one per DM block and 4-channel step k):
+// LDS of a work-group: int32 accumulator tile [tile][32], then `depth` staging
+// buffers of 4 rows, then `depth` records.
+constexpr int mfma_lds_bytes(int tile, int depth) { return tile * 32 * 4 + depth * (4 * kMfmaRow + kMfmaRec); }
+// Record layout (one per DM block and 4-channel step k; D = the variant's depth):
 //   [0, 128)    u8  8*r[d][4k+i] at 4d+i (d < 32, i < 4)
 //   [128, 192)  i16 e[d] = E[d] - min E of the channel block holding step k
 //   [192, 196)  u8  phase of the 4 staged rows (their start mod 16)
 //   [196, 200)  i32 rows of t' in 32-row tiles for that channel block
-//   [200, 204)  i32 1 if the channel block ends with step k
-//   [204, 220)  i32 16-aligned row starts (relative to the time tile) of step k + 2
-constexpr int kRecE = 128, kRecPhase = 192, kRecTiles = 196, kRecEnd = 200, kRecNextRs = 204;
+//   [200, 204)  i32 steps of the channel block from step k on (k included)
+//   [204, 208)  i32 16-byte chunks each row of step k + D - 1 needs
+//   [208, 224)  i32 16-aligned row starts (relative to the time tile) of step k + D - 1
+//   [224, 228)  i32 max e over the channel block's trials
+constexpr int kRecE = 128, kRecPhase = 192, kRecTiles = 196, kRecLeft = 200, kRecNextNeed = 204, kRecNextRs = 208, kRecMaxE = 224;
 extern const DedispVariant kDedispVariants[kNumDedispVariants];
 constexpr int kDefaultDedispVariant = 0;
 
@@ -106,6 +109,7 @@ struct DedispArgs {
     int32_t* out;
     int64_t out_pitch, n_out, ntile;
     const uint8_t* pad;
+    int64_t tile;    // output samples per work-group
 };
 
 }  // namespace aa
@@ -134,8 +138,8 @@ namespace aa {
 int prepare_variant(aa_plan_s* p, int variant);
 // Host tables of the matrix-core variant: DM blocks, 16-aligned staged-row starts
 // [nblk][nchan4] and the per-step records [nblk][nchan4 / 4][kMfmaRec].
-int build_mfma_tables(const aa_plan_s* p, std::vector<DmBlock>& blocks, std::vector<int32_t>& rsv,
-                      std::vector<uint8_t>& rec);
+int build_mfma_tables(const aa_plan_s* p, int tile, int depth, std::vector<DmBlock>& blocks,
+                      std::vector<int32_t>& rsv, std::vector<uint8_t>& rec);
 void free_tables(DedispTables& t);
 // Launchers (dedisp.hip, sps.hip). Arguments are validated by the callers.
 int launch_dedisperse(const aa_plan_s* p, int variant, const uint8_t* d_in, int64_t in_pitch, int64_t n_in,

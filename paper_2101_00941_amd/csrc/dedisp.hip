@@ -317,39 +317,21 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, int blk, int64_
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 typedef int32_t i32x16 __attribute__((ext_vector_type(16)));
 
-// The tiles of one step. Wave w owns tiles w + 8 j; a channel block has at least 32
-// tiles, so tiles j < 4 always exist and tiles 4..7 exist for j < nt. All LDS windows
-// are read first, then aligned, re-biased (x - 128) and contracted.
-__device__ __forceinline__ void mfma_step(i32x16 (&acc)[kMfmaTilesPerWave], const uint8_t* lds, int w0, int w1,
-                                          uint32_t u0, uint32_t u1, const i32x4& B, int nt) {
-    uint32_t x[8][3], y[8][3];
-    auto load = [&](int j) {
-        // tiles 4..7 use the base + 1024 so that ds_read2 offsets stay within 8 bits
-        const uint32_t* p0 = reinterpret_cast<const uint32_t*>(lds + w0 + 256 * j);
-        const uint32_t* p1 = reinterpret_cast<const uint32_t*>(lds + w1 + 256 * j);
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            x[j][i] = p0[i];
-            y[j][i] = p1[i];
-        }
-    };
-    auto mma = [&](int j) {
-        const i32x4 Av = {static_cast<int32_t>(__builtin_amdgcn_alignbyte(x[j][1], x[j][0], u0) ^ 0x80808080u),
-                          static_cast<int32_t>(__builtin_amdgcn_alignbyte(x[j][2], x[j][1], u0) ^ 0x80808080u),
-                          static_cast<int32_t>(__builtin_amdgcn_alignbyte(y[j][1], y[j][0], u1) ^ 0x80808080u),
-                          static_cast<int32_t>(__builtin_amdgcn_alignbyte(y[j][2], y[j][1], u1) ^ 0x80808080u)};
-        acc[j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(Av, B, acc[j], 0, 0, 0);
-    };
-#pragma unroll
-    for (int j = 0; j < 4; ++j) load(j);
-#pragma unroll
-    for (int j = 4; j < 8; ++j)
-        if (j < nt) load(j);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) mma(j);
-#pragma unroll
-    for (int j = 4; j < 8; ++j)
-        if (j < nt) mma(j);
+// s_waitcnt vmcnt(n) for a wave-uniform n in [0, 24].
+template <int N>
+__device__ __forceinline__ void vmcnt_le() {
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+__device__ __forceinline__ void wait_vmcnt(int n) {
+    switch (n) {
+#define AA_VM(N) \
+    case N: vmcnt_le<N>(); break;
+        AA_VM(0) AA_VM(1) AA_VM(2) AA_VM(3) AA_VM(4) AA_VM(5) AA_VM(6) AA_VM(7) AA_VM(8) AA_VM(9) AA_VM(10) AA_VM(11)
+        AA_VM(12) AA_VM(13) AA_VM(14) AA_VM(15) AA_VM(16) AA_VM(17) AA_VM(18) AA_VM(19) AA_VM(20) AA_VM(21) AA_VM(22)
+        AA_VM(23)
+#undef AA_VM
+        default: vmcnt_le<24>(); break;
+    }
 }
 
 // Matrix-core dedispersion of one (DM block, time tile), layout 4. The shift of a
@@ -362,134 +344,246 @@ __device__ __forceinline__ void mfma_step(i32x16 (&acc)[kMfmaTilesPerWave], cons
 // matrix B[(c, r)][d], computed exactly by v_mfma_i32_32x32x32_i8: rows are 32 values
 // of t', columns the 32 trials, and one step contracts 4 channels x 8 residuals.
 // Input bytes enter as x - 128 (signed 8-bit), and 128 * nchan is added back at the end.
-//  * 8 waves. Wave w owns the tiles w + 8 j (j < 8) of 32 rows of t' (a channel block
-//    needs 32 to 63 tiles) and holds their 32 x 32 int32 accumulators in registers.
+//  * W = 8 or 16 waves. Wave w owns the tiles w + W j of 32 rows of t' (a channel block
+//    needs TILE / 32 to 63 tiles, so a wave owns NT = TILE / (32 W) .. 64 / W of them)
+//    and holds their 32 x 32 int32 accumulators in registers. Each channel block runs a loop specialised
+//    for the wave's NT, so the hot loop has no per-tile branches; the loop is bound by
+//    instruction issue, not by the matrix cores.
 //  * At the end of a channel block, each accumulator row t' of trial d is added into
-//    the work-group's [1024][32] int32 tile in LDS at t = t' - e[d] (ds_add_u32). Lanes
+//    the work-group's [TILE][32] int32 tile in LDS at t = t' - e[d] (ds_add_u32). Lanes
 //    hold 32 distinct trials of one row, so these adds are conflict-free.
-//  * Input rows are staged 4 channels per step, 2048 bytes each, by direct
-//    global->LDS loads into a 3-deep ring, issued 2 steps ahead. Each step's table record
-//    (residuals, e, phases, tile count, row starts of step + 2) rides along in the
-//    same ring. Every wave issues exactly one data load per step, and wave 0 also the
-//    record, so "s_waitcnt vmcnt(1)" (wave 0: vmcnt(2)) before the step's barrier
-//    leaves only the newest step in flight.
+//  * Input rows are staged 4 channels per step, up to 2048 bytes each, by direct
+//    global->LDS loads into a ring of DEPTH buffers, issued DEPTH - 1 steps ahead.
+//    Each step's table record (residuals, e, phases, tile and step counts, and the row
+//    starts and lengths of the step DEPTH - 1 ahead) rides along in the same ring.
+//    Every wave issues exactly one data load per step, and wave 0 also the record, so
+//    waiting until only the newer steps' loads are in flight makes a step's data
+//    complete. Lanes past a row's needed length load a duplicate of its first chunk.
 //  * A lane (row m, half h) reads its two channels' windows as 3 aligned dwords each
 //    and aligns them with v_alignbyte_b32. Every staged chunk that a needed byte lives
 //    in is in range; chunks wholly outside [0, n_in16) are clamped to a valid address,
 //    and their bytes only reach rows that are never written out.
+struct MfmaCtx {
+    const DedispArgs* A;
+    const uint8_t* recg;   // this DM block's records
+    int64_t t0, last16;
+    int K4, wave, lane, m, h, row, half, vlane, ps;
+};
+
+template <int TILE, int DEPTH>
+struct MfmaLayout {
+    static constexpr int STAGE = 4 * kMfmaRow;
+    static constexpr int ACC = TILE * 32 * 4;
+    static constexpr int RING = ACC;                  // byte offsets into LDS
+    static constexpr int RECS = ACC + DEPTH * STAGE;
+};
+
+// Loads of step k into ring slot `slot`: each wave stages half a channel row
+// (16 bytes per lane, `need` chunks of the row), then wave 0 the step's record.
+template <int TILE, int DEPTH>
+__device__ __forceinline__ void mfma_issue(const MfmaCtx& cx, uint8_t* lds, int k, int slot, int rs, int need) {
+    using L = MfmaLayout<TILE, DEPTH>;
+    const DedispArgs& A = *cx.A;
+    if (cx.wave >= 8) return;                          // waves 0..7 stage the 8 half rows
+    const int c = 4 * k + cx.row;
+    const int v = cx.vlane < need ? cx.vlane : 0;
+    uint8_t* dst = lds + L::RING + slot * L::STAGE + cx.row * kMfmaRow + cx.half * 1024;
+    if (c < A.nchan) {
+        const int64_t first = cx.t0 + rs;               // wave-uniform
+        const int top = need < 64 * cx.half + 64 ? need : 64 * cx.half + 64;
+        const uint8_t* rowp = A.in + static_cast<int64_t>(c) * A.in_pitch;
+        if (first >= 0 && first + 16 * top <= A.n_in16) {
+            __builtin_amdgcn_global_load_lds(rowp + first + 16 * v, (lds_void*)dst, 16, 0, 0);
+        } else {
+            int64_t pos = first + 16 * v;
+            pos = pos < 0 ? 0 : (pos > cx.last16 ? cx.last16 : pos);
+            __builtin_amdgcn_global_load_lds(rowp + pos, (lds_void*)dst, 16, 0, 0);
+        }
+    } else {
+        __builtin_amdgcn_global_load_lds(A.pad + 16 * v, (lds_void*)dst, 16, 0, 0);
+    }
+    if (cx.wave == 0)
+        __builtin_amdgcn_global_load_lds(cx.recg + static_cast<int64_t>(k) * kMfmaRec + 4 * cx.lane,
+                                         (lds_void*)(lds + L::RECS + slot * kMfmaRec), 4, 0, 0);
+}
+
+// Wait until step k's loads are complete: the steps k + 1 .. k + DEPTH - 2 may still
+// be in flight (constant count in the steady state), then barrier.
+template <int DEPTH>
+__device__ __forceinline__ void mfma_wait(const MfmaCtx& cx, int k) {
+    if (k + DEPTH - 2 < cx.K4) {
+        if (cx.ps == 2)
+            vmcnt_le<2 * (DEPTH - 2)>();
+        else if (cx.ps == 1)
+            vmcnt_le<DEPTH - 2>();
+    } else {
+        wait_vmcnt((cx.K4 - 1 - k) * cx.ps);
+    }
+    __builtin_amdgcn_s_barrier();
+}
+
+// The steps [k0, k1) of one channel block, with NT tiles for this wave (tiles
+// wave + W j). `slot` is the ring slot of step k0 on entry and of step k1 on exit.
+template <int NT, int W, int TILE, int DEPTH>
+__device__ __forceinline__ void mfma_block(const MfmaCtx& cx, uint8_t* lds, int k0, int k1, int& slot,
+                                           i32x16 (&acc)[64 / W]) {
+    using L = MfmaLayout<TILE, DEPTH>;
+    const int lane_base = L::RING + 2 * cx.h * kMfmaRow + 32 * cx.wave + cx.m;
+#pragma unroll 1
+    for (int k = k0; k < k1; ++k) {
+        if (k > k0) mfma_wait<DEPTH>(cx, k);
+        const int rec = L::RECS + slot * kMfmaRec;
+        // every wave is done with the buffer of step k - 1: refill it with step k + DEPTH - 1
+        if (k + DEPTH - 1 < cx.K4) {
+            const int need = __builtin_amdgcn_readfirstlane(*reinterpret_cast<const int32_t*>(lds + rec + kRecNextNeed));
+            const int rs = __builtin_amdgcn_readfirstlane(
+                *reinterpret_cast<const int32_t*>(lds + rec + kRecNextRs + 4 * cx.row));
+            mfma_issue<TILE, DEPTH>(cx, lds, k + DEPTH - 1, slot == 0 ? DEPTH - 1 : slot - 1, rs, need);
+        }
+        // one-hot B: lane (trial m, half h) holds channels 2h, 2h+1 of the step
+        const uint32_t r32 = *reinterpret_cast<const uint32_t*>(lds + rec + 4 * cx.m);
+        const uint32_t ph = *reinterpret_cast<const uint16_t*>(lds + rec + kRecPhase + 2 * cx.h);
+        const uint32_t sh0 = (r32 >> (16 * cx.h)) & 0xFFu, sh1 = (r32 >> (16 * cx.h + 8)) & 0xFFu;
+        const uint64_t o0 = 1ull << sh0, o1 = 1ull << sh1;
+        const i32x4 B = {static_cast<int32_t>(o0), static_cast<int32_t>(o0 >> 32), static_cast<int32_t>(o1),
+                         static_cast<int32_t>(o1 >> 32)};
+        // data A: lane (row m, half h) reads 8-byte windows of channels 2h, 2h+1
+        const int base = lane_base + slot * L::STAGE;
+        const int a0 = base + static_cast<int>(ph & 0xFFu), a1 = base + kMfmaRow + static_cast<int>(ph >> 8);
+        const int w0 = a0 & ~3, w1 = a1 & ~3;
+        const uint32_t u0 = static_cast<uint32_t>(a0 & 3), u1 = static_cast<uint32_t>(a1 & 3);
+        uint32_t x[NT][3], y[NT][3];
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const uint32_t* p0 = reinterpret_cast<const uint32_t*>(lds + w0 + 32 * W * j);
+            const uint32_t* p1 = reinterpret_cast<const uint32_t*>(lds + w1 + 32 * W * j);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                x[j][i] = p0[i];
+                y[j][i] = p1[i];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const i32x4 Av = {static_cast<int32_t>(__builtin_amdgcn_alignbyte(x[j][1], x[j][0], u0) ^ 0x80808080u),
+                              static_cast<int32_t>(__builtin_amdgcn_alignbyte(x[j][2], x[j][1], u0) ^ 0x80808080u),
+                              static_cast<int32_t>(__builtin_amdgcn_alignbyte(y[j][1], y[j][0], u1) ^ 0x80808080u),
+                              static_cast<int32_t>(__builtin_amdgcn_alignbyte(y[j][2], y[j][1], u1) ^ 0x80808080u)};
+            acc[j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(Av, B, acc[j], 0, 0, 0);
+        }
+        slot = slot + 1 == DEPTH ? 0 : slot + 1;
+    }
+}
+
+template <int W, int TILE, int DEPTH>
 __device__ __forceinline__ void dedisp_mfma_tile(const DedispArgs& A, int blk, int64_t t0) {
-    constexpr int W = kMfmaWaves, TPW = kMfmaTilesPerWave;
-    constexpr int STAGE = 4 * kMfmaRow;
-    constexpr int RING = kMfmaAccBytes;                 // byte offsets into LDS
-    constexpr int RECS = kMfmaAccBytes + 3 * STAGE;
+    // wave w owns the tiles w + W j (j < TPW); a channel block has at least TILE / 32
+    // tiles, so each wave owns at least U of them
+    constexpr int TPW = 64 / W, U = TILE / (32 * W);
+    using L = MfmaLayout<TILE, DEPTH>;
+    static_assert((W == 8 || W == 16) && TILE % 32 == 0 && U >= 1 && U <= 4 && DEPTH >= 3 && DEPTH <= 13,
+                  "waves / tile / depth");
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     int32_t* acc_lds = reinterpret_cast<int32_t*>(lds);
+    MfmaCtx cx;
+    cx.A = &A;
+    cx.t0 = t0;
+    cx.last16 = A.n_in16 - 16;
+    cx.K4 = A.nchan_pad >> 2;
+    cx.recg = reinterpret_cast<const uint8_t*>(A.offs) + static_cast<int64_t>(blk) * cx.K4 * kMfmaRec;
     const int tid = threadIdx.x;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int lane = tid & 63, m = lane & 31, h = lane >> 5;
-    const int K4 = A.nchan_pad >> 2;
-    const uint8_t* recg = reinterpret_cast<const uint8_t*>(A.offs) + static_cast<int64_t>(blk) * K4 * kMfmaRec;
+    cx.wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    cx.lane = tid & 63;
+    cx.m = cx.lane & 31;
+    cx.h = cx.lane >> 5;
+    cx.row = cx.wave >> 1;
+    cx.half = cx.wave & 1;
+    cx.vlane = 64 * cx.half + cx.lane;
+    cx.ps = cx.wave == 0 ? 2 : (cx.wave < 8 ? 1 : 0);  // loads this wave issues per step
     const int32_t* rsv = A.base + static_cast<int64_t>(blk) * A.nchan_pad;
-    const int64_t last16 = A.n_in16 - 16;
 
-    // Loads of step k into ring slot `slot`: each wave stages half a channel row
-    // (16 bytes per lane), and wave 0 then the step's table record (4 bytes per lane).
-    static_assert(W == 8, "one wave per half row");
-    auto issue = [&](int k, int slot, int rs) {
-        {
-            const int row = wave >> 1, half = wave & 1;
-            const int c = 4 * k + row;
-            const int v = 64 * half + lane;
-            const uint8_t* src;
-            if (c < A.nchan) {
-                int64_t pos = t0 + rs + 16 * v;
-                pos = pos < 0 ? 0 : (pos > last16 ? last16 : pos);
-                src = A.in + static_cast<int64_t>(c) * A.in_pitch + pos;
-            } else {
-                src = A.pad + 16 * v;
-            }
-            __builtin_amdgcn_global_load_lds(src, (lds_void*)(lds + RING + slot * STAGE + row * kMfmaRow + half * 1024),
-                                             16, 0, 0);
-        }
-        if (wave == 0) {
-            __builtin_amdgcn_global_load_lds(recg + static_cast<int64_t>(k) * kMfmaRec + 4 * lane,
-                                             (lds_void*)(lds + RECS + slot * kMfmaRec), 4, 0, 0);
-        }
-    };
-
-    for (int i = tid; i < kMfmaAccBytes / 16; i += 64 * W) reinterpret_cast<u32x4*>(lds)[i] = u32x4{0u, 0u, 0u, 0u};
-    const int rs0 = __builtin_amdgcn_readfirstlane(rsv[wave >> 1]);
-    const int rs1 = K4 > 1 ? __builtin_amdgcn_readfirstlane(rsv[4 + (wave >> 1)]) : 0;
-    issue(0, 0, rs0);
-    if (K4 > 1) issue(1, 1, rs1);
+    for (int i = tid; i < L::ACC / 16; i += 64 * W) reinterpret_cast<u32x4*>(lds)[i] = u32x4{0u, 0u, 0u, 0u};
+    int rs_pro[DEPTH - 1];
+#pragma unroll
+    for (int j = 0; j < DEPTH - 1; ++j)
+        rs_pro[j] = j < cx.K4 ? __builtin_amdgcn_readfirstlane(rsv[4 * j + cx.row]) : 0;
+#pragma unroll
+    for (int j = 0; j < DEPTH - 1; ++j)
+        if (j < cx.K4) mfma_issue<TILE, DEPTH>(cx, lds, j, j, rs_pro[j], kMfmaRow / 16);
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
 
     i32x16 acc[TPW];
 #pragma unroll
     for (int j = 0; j < TPW; ++j) acc[j] = i32x16{};
+    const uint32_t acc_base =
+        static_cast<uint32_t>(reinterpret_cast<uintptr_t>((__attribute__((address_space(3))) int32_t*)acc_lds));
     int slot = 0;
-    for (int k = 0; k < K4; ++k) {
-        if (k + 1 >= K4)
-            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        else if (wave == 0)
-            asm volatile("s_waitcnt vmcnt(2)" ::: "memory");
-        else
-            asm volatile("s_waitcnt vmcnt(1)" ::: "memory");
-        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-        __builtin_amdgcn_s_barrier();
-        const int rec = RECS + slot * kMfmaRec;
-        auto issue_ahead = [&]() {
-            const int rs = __builtin_amdgcn_readfirstlane(
-                *reinterpret_cast<const int32_t*>(lds + rec + kRecNextRs + 4 * (wave >> 1)));
-            issue(k + 2, slot == 0 ? 2 : slot - 1, rs);
-        };
-        // one-hot B: lane (trial m, half h) holds channels 2h, 2h+1 of the step
-        const uint32_t r32 = *reinterpret_cast<const uint32_t*>(lds + rec + 4 * m);
-        const uint32_t sh0 = (r32 >> (16 * h)) & 0xFFu, sh1 = (r32 >> (16 * h + 8)) & 0xFFu;
-        const uint64_t o0 = 1ull << sh0, o1 = 1ull << sh1;
-        const i32x4 B = {static_cast<int32_t>(o0), static_cast<int32_t>(o0 >> 32), static_cast<int32_t>(o1),
-                         static_cast<int32_t>(o1 >> 32)};
-        const int nr = __builtin_amdgcn_readfirstlane(*reinterpret_cast<const int32_t*>(lds + rec + kRecTiles));
-        const int endf = __builtin_amdgcn_readfirstlane(*reinterpret_cast<const int32_t*>(lds + rec + kRecEnd));
-        const uint32_t ph = *reinterpret_cast<const uint16_t*>(lds + rec + kRecPhase + 2 * h);
-        // A flush (LDS adds) waits for every load in flight, so a step that ends a
-        // channel block issues its loads after the flush.
-        if (k + 2 < K4 && !endf) issue_ahead();
-        // data A: lane (row m, half h) reads 8-byte windows of channels 2h, 2h+1;
-        // tile j of this wave starts at row 32 (wave + 8 j)
-        const int base = RING + slot * STAGE + 2 * h * kMfmaRow + 32 * wave + m;
-        const int a0 = base + static_cast<int>(ph & 0xFFu), a1 = base + kMfmaRow + static_cast<int>(ph >> 8);
-        const int w0 = a0 & ~3, w1 = a1 & ~3;
-        const uint32_t u0 = static_cast<uint32_t>(a0 & 3), u1 = static_cast<uint32_t>(a1 & 3);
-        static_assert(TPW == 8 && W == 8, "tile ownership below");
-        mfma_step(acc, lds, w0, w1, u0, u1, B, (nr - wave + 7) >> 3);
-        if (endf) {
-            // accumulator register i of lane (m, h) holds row 8 (i / 4) + 4 h + i % 4 of
-            // the tile and trial m
-            const int e = *reinterpret_cast<const int16_t*>(lds + rec + kRecE + 2 * m);
+    for (int k0 = 0; k0 < cx.K4;) {
+        mfma_wait<DEPTH>(cx, k0);
+        const int rec0 = L::RECS + slot * kMfmaRec;
+        const int nr = __builtin_amdgcn_readfirstlane(*reinterpret_cast<const int32_t*>(lds + rec0 + kRecTiles));
+        const int k1 = k0 + __builtin_amdgcn_readfirstlane(*reinterpret_cast<const int32_t*>(lds + rec0 + kRecLeft));
+        const int nt = (nr - cx.wave + W - 1) / W;      // tiles of this wave, U .. TPW
+        if constexpr (W == 8) {
+            switch (nt) {
+                case 8: mfma_block<8, W, TILE, DEPTH>(cx, lds, k0, k1, slot, acc); break;
+                case 7: mfma_block<7, W, TILE, DEPTH>(cx, lds, k0, k1, slot, acc); break;
+                case 6: mfma_block<6, W, TILE, DEPTH>(cx, lds, k0, k1, slot, acc); break;
+                case 5: mfma_block<5, W, TILE, DEPTH>(cx, lds, k0, k1, slot, acc); break;
+                case 4: mfma_block<4, W, TILE, DEPTH>(cx, lds, k0, k1, slot, acc); break;
+                default: mfma_block<U, W, TILE, DEPTH>(cx, lds, k0, k1, slot, acc); break;
+            }
+        } else {
+            switch (nt) {
+                case 4: mfma_block<4, W, TILE, DEPTH>(cx, lds, k0, k1, slot, acc); break;
+                case 3: mfma_block<3, W, TILE, DEPTH>(cx, lds, k0, k1, slot, acc); break;
+                case 2: mfma_block<2, W, TILE, DEPTH>(cx, lds, k0, k1, slot, acc); break;
+                default: mfma_block<U, W, TILE, DEPTH>(cx, lds, k0, k1, slot, acc); break;
+            }
+        }
+        // flush: accumulator register i of lane (m, h) holds row 8 (i / 4) + 4 h + i % 4
+        // of the tile and trial m, which goes to t = row - e[m]. The adds are issued as
+        // inline ds_add_u32 so that the compiler does not wait for the staging loads in
+        // flight (they write other LDS bytes); the barrier after the loop orders them
+        // before the final read. A tile whose rows land in [0, TILE) for every e in
+        // [0, max e] adds with immediate offsets and no checks.
+        const int last = slot == 0 ? DEPTH - 1 : slot - 1;   // slot of step k1 - 1
+        const int lrec = L::RECS + last * kMfmaRec;
+        const int e = *reinterpret_cast<const int16_t*>(lds + lrec + kRecE + 2 * cx.m);
+        const int emax = __builtin_amdgcn_readfirstlane(*reinterpret_cast<const int32_t*>(lds + lrec + kRecMaxE));
 #pragma unroll
-            for (int j = 0; j < TPW; ++j) {
-                const int q = wave + 8 * j;
-                if (q < nr) {
+        for (int j = 0; j < TPW; ++j) {
+            const int q = cx.wave + W * j;
+            if (j < U || q < nr) {
+                if (32 * q >= emax && 32 * q + 32 <= TILE) {
+                    const uint32_t tb = acc_base + 4u * static_cast<uint32_t>(cx.m + 32 * (32 * q + 4 * cx.h - e));
+#define AA_FLUSH(I) \
+    asm volatile("ds_add_u32 %0, %1 offset:%2" ::"v"(tb), "v"(acc[j][I]), "n"(128 * (8 * ((I) >> 2) + ((I) & 3))) : "memory");
+                    AA_FLUSH(0) AA_FLUSH(1) AA_FLUSH(2) AA_FLUSH(3) AA_FLUSH(4) AA_FLUSH(5) AA_FLUSH(6) AA_FLUSH(7)
+                    AA_FLUSH(8) AA_FLUSH(9) AA_FLUSH(10) AA_FLUSH(11) AA_FLUSH(12) AA_FLUSH(13) AA_FLUSH(14) AA_FLUSH(15)
+#undef AA_FLUSH
+                } else {
 #pragma unroll
                     for (int i = 0; i < 16; ++i) {
-                        const int t = 32 * q + 8 * (i >> 2) + 4 * h + (i & 3) - e;
-                        if (static_cast<unsigned>(t) < static_cast<unsigned>(kTimeTile))
-                            __hip_atomic_fetch_add(acc_lds + 32 * t + m, acc[j][i], __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+                        const int t = 32 * q + 8 * (i >> 2) + 4 * cx.h + (i & 3) - e;
+                        if (static_cast<unsigned>(t) < static_cast<unsigned>(TILE)) {
+                            const uint32_t addr = acc_base + 4u * static_cast<uint32_t>(32 * t + cx.m);
+                            asm volatile("ds_add_u32 %0, %1" ::"v"(addr), "v"(acc[j][i]) : "memory");
+                        }
                     }
                 }
-                acc[j] = i32x16{};
             }
-            if (k + 2 < K4) issue_ahead();
+            acc[j] = i32x16{};
         }
-        slot = slot == 2 ? 0 : slot + 1;
+        k0 = k1;
     }
+    asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
     __syncthreads();
 
     const DmBlock b = A.blocks[blk];
     const int32_t corr = 128 * A.nchan;
 #pragma unroll 1
-    for (int it = 0; it < kTimeTile * 32 / 4 / (64 * W); ++it) {
+    for (int it = 0; it < TILE * 32 / 4 / (64 * W); ++it) {
         const int idx = tid + 64 * W * it;
         const int d = idx & 31, tq = idx >> 5;
         int32_t v[4];
@@ -510,11 +604,11 @@ __device__ __forceinline__ void dedisp_mfma_tile(const DedispArgs& A, int blk, i
     }
 }
 
-template <int DPW, int W, int LAYOUT>
+template <int DPW, int W, int LAYOUT, int TILE = kTimeTile, int DEPTH = 2>
 __global__ __launch_bounds__(64 * W) void dedisp_kernel(DedispArgs a) {
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
     if constexpr (LAYOUT == 4)
-        dedisp_mfma_tile(a, bid % a.nblk, static_cast<int64_t>(bid / a.nblk) * kTimeTile);
+        dedisp_mfma_tile<W, TILE, DEPTH>(a, bid % a.nblk, static_cast<int64_t>(bid / a.nblk) * TILE);
     else
         dedisp_tile<DPW, W, LAYOUT>(a, bid % a.nblk, static_cast<int64_t>(bid / a.nblk) * kTimeTile);
 }
@@ -525,7 +619,7 @@ __global__ __launch_bounds__(64 * W) void dedisp_kernel(DedispArgs a) {
 // of the same beam (their input rows overlap). A work-group reads the item index from
 // the counter, finds its beam by binary search over item_begin, and exits when the
 // index passes the total: every work-group reaches that exit.
-template <int DPW, int W, int LAYOUT>
+template <int DPW, int W, int LAYOUT, int TILE = kTimeTile, int DEPTH = 2>
 __global__ __launch_bounds__(64 * W) void dedisp_batch_kernel(const DedispArgs* __restrict__ args,
                                                               const int64_t* __restrict__ item_begin, int nbeams,
                                                               int64_t total, unsigned long long* counter) {
@@ -548,7 +642,7 @@ __global__ __launch_bounds__(64 * W) void dedisp_batch_kernel(const DedispArgs* 
         const DedispArgs a = args[lo];
         const int64_t local = it - item_begin[lo];
         if constexpr (LAYOUT == 4)
-            dedisp_mfma_tile(a, static_cast<int>(local % a.nblk), (local / a.nblk) * kTimeTile);
+            dedisp_mfma_tile<W, TILE, DEPTH>(a, static_cast<int>(local % a.nblk), (local / a.nblk) * TILE);
         else
             dedisp_tile<DPW, W, LAYOUT>(a, static_cast<int>(local % a.nblk), (local / a.nblk) * kTimeTile);
         __syncthreads();   // the next item restages LDS buffer 0
@@ -563,7 +657,7 @@ typedef void (*DedispBatchFn)(const DedispArgs*, const int64_t*, int, int64_t, u
 // Indexed by DedispVariant::id (tiling.cpp).
 #define AA_VARIANTS(K)                                                                           \
     K<4, 4, 1>, K<2, 8, 1>, K<4, 8, 1>, K<2, 16, 1>, K<2, 8, 0>, K<4, 4, 0>, K<2, 8, 3>, K<4, 4, 3>, \
-        K<2, 8, 2>, K<4, 8, 2>, K<4, 4, 2>, K<4, 8, 4>
+        K<2, 8, 2>, K<4, 8, 2>, K<4, 4, 2>, K<4, 8, 4, 1024, 3>, K<2, 16, 4, 1024, 3>, K<2, 16, 4, 768, 7>
 const DedispFn kKernels[kNumDedispVariants] = {AA_VARIANTS(dedisp_kernel)};
 const DedispBatchFn kBatchKernels[kNumDedispVariants] = {AA_VARIANTS(dedisp_batch_kernel)};
 #undef AA_VARIANTS
@@ -590,7 +684,9 @@ DedispArgs dedisp_args(const aa_plan_s* p, int variant, const uint8_t* d_in, int
     a.out_pitch = out_pitch;
     a.n_out = n_in - p->maxshift;
     a.row = T.max_row;
-    a.ntile = (a.n_out + kTimeTile - 1) / kTimeTile;
+    const int tile = kDedispVariants[variant].tile;
+    a.tile = tile;
+    a.ntile = (a.n_out + tile - 1) / tile;
     a.pad = T.d_pad;
     return a;
 }
@@ -603,7 +699,7 @@ int launch_dedisperse(const aa_plan_s* p, int variant, const uint8_t* d_in, int6
     const DedispArgs a = dedisp_args(p, variant, d_in, in_pitch, n_in, d_out, out_pitch);
     const int64_t grid = a.ntile * a.nblk;
     if (grid > 0x7fffffff) return fail(AA_EINVAL, "aa_dedisperse: too many tiles for one launch");
-    const size_t lds = V.layout == 4 ? static_cast<size_t>(kMfmaLds) : static_cast<size_t>(2 * kChanPerPass) * T.max_row;
+    const size_t lds = V.layout == 4 ? static_cast<size_t>(V.lds_bytes) : static_cast<size_t>(2 * kChanPerPass) * T.max_row;
     hipLaunchKernelGGL(kKernels[variant], dim3(static_cast<unsigned>(grid)), dim3(64 * V.waves), lds, stream, a);
     AA_HIP(hipGetLastError());
     return AA_OK;
@@ -612,7 +708,7 @@ int launch_dedisperse(const aa_plan_s* p, int variant, const uint8_t* d_in, int6
 int launch_dedisperse_batch(int variant, const DedispArgs* d_args, const int64_t* d_item_begin, int nbeams,
                             int64_t total, unsigned long long* d_counter, int max_row, hipStream_t stream) {
     const DedispVariant& V = kDedispVariants[variant];
-    const size_t lds = V.layout == 4 ? static_cast<size_t>(kMfmaLds) : static_cast<size_t>(2 * kChanPerPass) * max_row;
+    const size_t lds = V.layout == 4 ? static_cast<size_t>(V.lds_bytes) : static_cast<size_t>(2 * kChanPerPass) * max_row;
     int dev = 0, cus = 0, per_cu = 0;
     AA_HIP(hipGetDevice(&dev));
     AA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));

@@ -11,18 +11,21 @@ namespace aa {
 // LDS budgets are sized so that 3 (52 KB) or 2 (80 KB) work-groups fit in one CU's
 // 160 KB of LDS.
 const DedispVariant kDedispVariants[kNumDedispVariants] = {
-    {0, 4, 4, 53248, 1},    // 256 threads, 16 trials per block, interleaved lanes
-    {1, 8, 2, 53248, 1},    // 512 threads, 16 trials per block, interleaved lanes
-    {2, 8, 4, 81920, 1},    // 512 threads, 32 trials per block, interleaved lanes
-    {3, 16, 2, 81920, 1},   // 1024 threads, 32 trials per block, interleaved lanes
-    {4, 8, 2, 53248, 0},    // 512 threads, 16 trials per block, contiguous lanes
-    {5, 4, 4, 53248, 0},    // 256 threads, 16 trials per block, contiguous lanes
-    {6, 8, 2, 53248, 3},    // 512 threads, 16 trials per block, contiguous lanes, 16-way switch
-    {7, 4, 4, 53248, 3},    // 256 threads, 16 trials per block, contiguous lanes, 16-way switch
-    {8, 8, 2, 53248, 2},    // 512 threads, 16 trials per block, interleaved, equal-offset reuse
-    {9, 8, 4, 81920, 2},    // 512 threads, 32 trials per block, interleaved, equal-offset reuse
-    {10, 4, 4, 53248, 2},   // 256 threads, 16 trials per block, interleaved, equal-offset reuse
-    {11, kMfmaWaves, 4, kMfmaLds, 4},   // 512 threads, 32 trials per block, i8 matrix cores
+    {0, 4, 4, 53248, 1, kTimeTile, 2},    // 256 threads, 16 trials per block, interleaved lanes
+    {1, 8, 2, 53248, 1, kTimeTile, 2},    // 512 threads, 16 trials per block, interleaved lanes
+    {2, 8, 4, 81920, 1, kTimeTile, 2},    // 512 threads, 32 trials per block, interleaved lanes
+    {3, 16, 2, 81920, 1, kTimeTile, 2},   // 1024 threads, 32 trials per block, interleaved lanes
+    {4, 8, 2, 53248, 0, kTimeTile, 2},    // 512 threads, 16 trials per block, contiguous lanes
+    {5, 4, 4, 53248, 0, kTimeTile, 2},    // 256 threads, 16 trials per block, contiguous lanes
+    {6, 8, 2, 53248, 3, kTimeTile, 2},    // 512 threads, 16 trials per block, contiguous lanes, 16-way switch
+    {7, 4, 4, 53248, 3, kTimeTile, 2},    // 256 threads, 16 trials per block, contiguous lanes, 16-way switch
+    {8, 8, 2, 53248, 2, kTimeTile, 2},    // 512 threads, 16 trials per block, interleaved, equal-offset reuse
+    {9, 8, 4, 81920, 2, kTimeTile, 2},    // 512 threads, 32 trials per block, interleaved, equal-offset reuse
+    {10, 4, 4, 53248, 2, kTimeTile, 2},   // 256 threads, 16 trials per block, interleaved, equal-offset reuse
+    // 32 trials per block, i8 matrix cores; waves, time tile and staging depth vary
+    {11, 8, 4, mfma_lds_bytes(1024, 3), 4, 1024, 3},    // 512 threads, 8 tiles per wave
+    {12, 16, 2, mfma_lds_bytes(1024, 3), 4, 1024, 3},   // 1024 threads, 4 tiles per wave
+    {13, 16, 2, mfma_lds_bytes(768, 7), 4, 768, 7},     // 1024 threads, 4 tiles per wave
 };
 
 void free_tables(DedispTables& t) {
@@ -46,7 +49,7 @@ int upload(T** dst, const std::vector<T>& src) {
 //  * DM blocks: up to 32 consecutive trials such that every 4-channel step on its own
 //    has a residual range below 8 (so a channel block always holds at least one step)
 //    and, for every channel, the spread of f over the block's trials is at most
-//    (kMfmaMaxTiles * 32 - kTimeTile). The spread of E over a channel block is bounded
+//    (kMfmaMaxTiles * 32 - tile). The spread of E over a channel block is bounded
 //    by that, so a channel block never needs more than kMfmaMaxTiles tiles of t'.
 //    A single trial always qualifies (f = 0).
 //  * Channel blocks: greedy runs of 4-channel steps whose residual range stays below 8.
@@ -55,12 +58,14 @@ int upload(T** dst, const std::vector<T>& src) {
 //  * Padded channels (c >= nchan) are staged from a row of 0x80 bytes, which the kernel
 //    maps to 0, so their residuals are 0. Absent trials of a short block have r = 0,
 //    e = 0 and are not written out.
-int build_mfma_tables(const aa_plan_s* p, std::vector<DmBlock>& blocks, std::vector<int32_t>& rsv,
-                      std::vector<uint8_t>& rec) {
+int build_mfma_tables(const aa_plan_s* p, int tile, int depth, std::vector<DmBlock>& blocks,
+                      std::vector<int32_t>& rsv, std::vector<uint8_t>& rec) {
     const int nchan = p->nchan;
     const int nchan4 = (nchan + 3) & ~3;
     const int K4 = nchan4 / 4;
-    const int spread_max = kMfmaMaxTiles * 32 - kTimeTile;
+    const int spread_max = kMfmaMaxTiles * 32 - tile;
+    if (tile % 32 || tile < 256 || spread_max < 0 || depth < 3)
+        return fail(AA_EINVAL, "matrix-core tiling: bad tile or depth");
     auto S = [&](int d, int c) { return p->shifts[static_cast<size_t>(d) * nchan + c]; };
     blocks.clear();
     std::vector<int32_t> fmin(nchan), fmax(nchan);
@@ -130,7 +135,7 @@ int build_mfma_tables(const aa_plan_s* p, std::vector<DmBlock>& blocks, std::vec
                 emin = std::min(emin, lo[i]);
                 emax = std::max(emax, lo[i]);
             }
-            const int tiles = (emax - emin + kTimeTile + 31) / 32;
+            const int tiles = (emax - emin + tile + 31) / 32;
             if (tiles > kMfmaMaxTiles) return fail(AA_EINVAL, "matrix-core tiling: channel block spread too large");
             for (int k = k0; k < k1; ++k) {
                 uint8_t* rk = R + static_cast<size_t>(k) * kMfmaRec;
@@ -148,25 +153,34 @@ int build_mfma_tables(const aa_plan_s* p, std::vector<DmBlock>& blocks, std::vec
                     const int16_t e = static_cast<int16_t>(lo[i] - emin);
                     std::memcpy(rk + kRecE + 2 * i, &e, 2);
                 }
-                const int32_t end = k + 1 == k1 ? 1 : 0;
+                const int32_t left = k1 - k, emax_rel = emax - emin;
                 std::memcpy(rk + kRecTiles, &tiles, 4);
-                std::memcpy(rk + kRecEnd, &end, 4);
+                std::memcpy(rk + kRecLeft, &left, 4);
+                std::memcpy(rk + kRecMaxE, &emax_rel, 4);
             }
             k0 = k1;
         }
-        // row starts of step k + 2, read by the kernel when it issues that step's loads
-        for (int k = 0; k + 2 < K4; ++k)
-            std::memcpy(R + static_cast<size_t>(k) * kMfmaRec + kRecNextRs, &rsv[bi * nchan4 + 4 * (k + 2)], 16);
+        // row starts and lengths of step k + depth - 1, read by the kernel when it issues
+        // that step's loads. A row needs the bytes [0, 32 tiles + phase + 11).
+        for (int k = 0; k + depth - 1 < K4; ++k) {
+            uint8_t* rk = R + static_cast<size_t>(k) * kMfmaRec;
+            const uint8_t* rn = R + static_cast<size_t>(k + depth - 1) * kMfmaRec;
+            std::memcpy(rk + kRecNextRs, &rsv[bi * nchan4 + 4 * (k + depth - 1)], 16);
+            int32_t tiles;
+            std::memcpy(&tiles, rn + kRecTiles, 4);
+            const int32_t need = std::min(kMfmaRow / 16, (32 * tiles + 15 + 11 + 15) / 16);
+            std::memcpy(rk + kRecNextNeed, &need, 4);
+        }
     }
     return AA_OK;
 }
 
 namespace {
-int prepare_mfma(const aa_plan_s* p, DedispTables& t) {
+int prepare_mfma(const aa_plan_s* p, const DedispVariant& V, DedispTables& t) {
     std::vector<DmBlock> blocks;
     std::vector<int32_t> rsv;
     std::vector<uint8_t> rec;
-    const int rc0 = build_mfma_tables(p, blocks, rsv, rec);
+    const int rc0 = build_mfma_tables(p, V.tile, V.depth, blocks, rsv, rec);
     if (rc0 != AA_OK) return rc0;
     t.bd = 32;
     t.nchan_pad = (p->nchan + 3) & ~3;
@@ -192,7 +206,7 @@ int prepare_variant(aa_plan_s* p, int v) {
     if (V.layout == 4) {
         DedispTables t;
         t.variant = v;
-        const int rc = prepare_mfma(p, t);
+        const int rc = prepare_mfma(p, V, t);
         if (rc != AA_OK) {
             free_tables(t);
             return rc;

@@ -73,6 +73,8 @@ extern "C" int aa_variant_info(int32_t v, aa_variant_t* out) {
     out->trials_per_block = V.waves * V.dpw;
     out->lds_bytes = V.lds_bytes;
     out->layout = V.layout;
+    out->time_tile = V.tile;
+    out->depth = V.depth;
     return AA_OK;
 }
 
