@@ -33,6 +33,15 @@ CU, CLOCK_GHZ, LANES = 256, 2.4, 64
 # int32 VALU adds: 256 CU x 64 lanes x 2.4 GHz = 39.3 T/s. The kernel adds bytes as
 # packed 16-bit pairs inside 32-bit adds, i.e. 2 byte-adds per lane operation.
 ALU_PEAK_TOPS = 2 * CU * LANES * CLOCK_GHZ / 1000.0   # 78.6 T byte-adds/s
+# Dense int8 matrix-core peak (v_mfma_i32_*_i8), TOP/s.
+I8_MFMA_PEAK_TOPS = 5000.0
+# HBM bytes per launch of the dedispersion kernel (FETCH_SIZE x 2.000 + WRITE_SIZE x
+# 1.000 per dispatch, scaled by a 1 GiB copy), from the counter runs summarised in
+# profiles/dedisp_*_survey_4096ch_1M.md. Keyed by (workload, variant); valid only for
+# the kernel code those counters were taken on.
+TRAFFIC_BYTES = {
+    ("survey_4096ch_1M", 12): 181.8e9 + 12.14e9,
+}
 
 
 def log(*a):
@@ -393,6 +402,19 @@ def main():
     adds = ndm * n_dd * nchan
     achieved = adds / (ms_dedisp * 1e-3) / 1e12
     value = ndm * n_dd / (ms_step * 1e-3)
+    vinfo = Plan.variants()[plan.variant]
+    traffic = TRAFFIC_BYTES.get((w["name"], plan.variant)) if not a.ndm else None
+    if vinfo["layout"] == 4:
+        # a contraction on the i8 matrix cores, priced against their dense peak; one op
+        # per useful byte add (the one-hot weights are not counted)
+        roofline = {"bound": "mfma", "dtype": "i8", "kernel": "dedisp_kernel (i8 matrix cores)",
+                    "achieved": achieved, "peak": I8_MFMA_PEAK_TOPS, "unit": "TOP/s",
+                    "frac": achieved / I8_MFMA_PEAK_TOPS, "traffic": traffic, "per_launch_ops": adds,
+                    "ms_per_launch": ms_dedisp, "alu_peak": ALU_PEAK_TOPS, "alu_frac": achieved / ALU_PEAK_TOPS}
+    else:
+        roofline = {"bound": "alu", "kernel": "dedisp_kernel", "achieved": achieved, "peak": ALU_PEAK_TOPS,
+                    "unit": "TOP/s", "frac": achieved / ALU_PEAK_TOPS, "traffic": traffic,
+                    "per_launch_ops": adds, "ms_per_launch": ms_dedisp}
     res = {
         "metric": "DM-trial*samples/s per GPU (dedispersion + single-pulse search)",
         "value": value,
@@ -410,9 +432,7 @@ def main():
                    "dm_max": float(w["dms"][-1]), "widths": w["widths"], "stat_block": info["stat_block"],
                    "maxshift": info["maxshift"], "mode": "resident input, one stream",
                    "dedisp_variant": plan.variant},
-        "roofline": {"bound": "alu", "kernel": "dedisp_kernel", "achieved": achieved, "peak": ALU_PEAK_TOPS,
-                     "unit": "TOP/s", "frac": achieved / ALU_PEAK_TOPS, "traffic": None,
-                     "per_launch_ops": adds, "ms_per_launch": ms_dedisp},
+        "roofline": roofline,
         "kernels_ms": {"dedisperse": ms_dedisp, "single_pulse": ms_sps},
         "candidates": int(h_count.item()),
     }
