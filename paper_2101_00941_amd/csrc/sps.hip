@@ -86,9 +86,10 @@ __global__ __launch_bounds__(256) void sps_stats_kernel(const int32_t* __restric
 constexpr int kHaloRows = kSpsRows + 2;
 constexpr int kHaloCols = kSpsTile + 2;
 // LDS region shared by the exact path (float64 best per halo cell) and the float32
-// screen (centres, fractions, r, best32 and its error bound)
+// screen (per row: negated centres, fractions x r, r, max r; per inner cell: best32 and
+// its error bound)
 constexpr int kExactBytes = kHaloRows * kHaloCols * 8;
-constexpr int kScreenBytes = kHaloRows * kMaxWidths * (8 + 4 + 4) + kHaloRows * kHaloCols * (4 + 4);
+constexpr int kScreenBytes = kHaloRows * kMaxWidths * (4 + 4 + 4) + kHaloRows * 4 + kSpsRows * kSpsTile * (4 + 4);
 constexpr int kBestBytes = ((kExactBytes > kScreenBytes ? kExactBytes : kScreenBytes) + 15) / 16 * 16;
 
 // Exact value of one halo cell: best S/N over the widths, float64, same operation order
@@ -185,42 +186,66 @@ __global__ __launch_bounds__(256) void sps_detect_kernel(
             best[i] = exact_best(pre, pw, nrm, sc, r, c, d >= 0 && d < ndm && t >= lo && t < hi);
         }
     } else {
-        // float32 screen: per row and width, the integer centre c = rint(w*mu), the
-        // fraction (w*mu - c) and r as floats
-        int64_t* cen = reinterpret_cast<int64_t*>(best);                    // [kHaloRows][kMaxWidths]
-        float* frac = reinterpret_cast<float*>(cen + kHaloRows * kMaxWidths);
-        float* r32 = frac + kHaloRows * kMaxWidths;
-        float* b32 = r32 + kHaloRows * kMaxWidths;                          // [kHaloRows][kHaloCols]
-        float* e32 = b32 + kHaloRows * kHaloCols;
+        // float32 screen of the inner cells. Per row and width: the integer centre
+        // c = rint(w*mu) (negated), f*r with the fraction f = w*mu - c, and r, as floats.
+        // For a start t, dv = S - c is exact in int32 (the launcher takes this path only
+        // when every window sum is below 2^31), x = float(dv) is within 2^-24 |x|, and
+        // snr32 = fma(x, r, -f*r) is within 2^-20 (|S/N| + r + 1) of the float64 S/N.
+        int32_t* ncen = reinterpret_cast<int32_t*>(best);                   // [kHaloRows][kMaxWidths]
+        float* fr = reinterpret_cast<float*>(ncen + kHaloRows * kMaxWidths);
+        float* r32 = fr + kHaloRows * kMaxWidths;
+        float* rmx = r32 + kHaloRows * kMaxWidths;                          // [kHaloRows]
+        float* b32 = rmx + kHaloRows;                                       // [kSpsRows][kSpsTile]
+        float* e32 = b32 + kSpsRows * kSpsTile;
         for (int i = tid; i < kHaloRows * sc.nw; i += 256) {
             const int r = i / sc.nw, k = i - r * sc.nw;
             const double wmu = nrm[r * 2 * kMaxWidths + k];
             const double c = __builtin_rint(wmu);
-            cen[r * kMaxWidths + k] = static_cast<int64_t>(c);
-            frac[r * kMaxWidths + k] = static_cast<float>(wmu - c);
-            r32[r * kMaxWidths + k] = static_cast<float>(nrm[r * 2 * kMaxWidths + sc.nw + k]);
+            const float rr = static_cast<float>(nrm[r * 2 * kMaxWidths + sc.nw + k]);
+            ncen[r * kMaxWidths + k] = -static_cast<int32_t>(c);
+            fr[r * kMaxWidths + k] = static_cast<float>(wmu - c) * rr;
+            r32[r * kMaxWidths + k] = rr;
+        }
+        if (tid < kHaloRows) {
+            float m = 0.0f;
+            for (int k = 0; k < sc.nw; ++k) m = fmaxf(m, static_cast<float>(nrm[tid * 2 * kMaxWidths + sc.nw + k]));
+            rmx[tid] = m;
         }
         __syncthreads();
-        for (int i = tid; i < kHaloRows * kHaloCols; i += 256) {
-            const int r = i / kHaloCols, c = i - r * kHaloCols;
-            const int d = d0 - 1 + r;
-            const int64_t t = tt0 - 1 + c;
-            float v = -__builtin_huge_valf(), amax = 0.0f, rmax = 0.0f;
-            if (d >= 0 && d < ndm && t >= lo && t < hi) {
-                const uint32_t* pr = pre + r * pw + c;
-                for (int k = 0; k < sc.nw; ++k) {
-                    const int64_t dv = static_cast<int64_t>(pr[sc.widths[k]] - pr[0]) - cen[r * kMaxWidths + k];
-                    const float x = static_cast<float>(static_cast<int32_t>(dv >> 12)) * 4096.0f +
-                                    static_cast<float>(static_cast<int32_t>(dv & 4095));
-                    const float rr = r32[r * kMaxWidths + k];
-                    const float snr = (x - frac[r * kMaxWidths + k]) * rr;
-                    v = (k == 0 || snr > v) ? snr : v;
-                    amax = fmaxf(amax, fabsf(snr));
-                    rmax = fmaxf(rmax, rr);
+        // wave w screens inner rows w and w + 4, lanes run over 4 chunks of 64 starts
+        const int wave = tid >> 6, lane = tid & 63;
+        for (int ri = wave; ri < kSpsRows; ri += 4) {
+            const int r = ri + 1;
+            const uint32_t* pr = pre + r * pw + 1 + lane;   // start tt0 + 64 q + lane
+            uint32_t neg0[4];
+            float v[4], am[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                neg0[q] = 0u - pr[64 * q];
+                v[q] = -__builtin_huge_valf();
+                am[q] = 0.0f;
+            }
+            for (int k = 0; k < sc.nw; ++k) {
+                const int w = sc.widths[k];
+                const uint32_t nc = static_cast<uint32_t>(ncen[r * kMaxWidths + k]);
+                const float rr = r32[r * kMaxWidths + k], nfr = -fr[r * kMaxWidths + k];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int32_t dv = static_cast<int32_t>(pr[64 * q + w] + neg0[q] + nc);
+                    const float snr = __builtin_fmaf(static_cast<float>(dv), rr, nfr);
+                    v[q] = fmaxf(v[q], snr);
+                    am[q] = fmaxf(am[q], fabsf(snr));
                 }
             }
-            b32[i] = v;
-            e32[i] = 9.5367431640625e-07f * (amax + rmax + 1.0f);   // 2^-20
+            const int d = d0 + ri;
+            const float rm = rmx[r];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t t = tt0 + 64 * q + lane;
+                const bool ok = d < ndm && t >= lo && t < hi;
+                b32[ri * kSpsTile + 64 * q + lane] = ok ? v[q] : -__builtin_huge_valf();
+                e32[ri * kSpsTile + 64 * q + lane] = 9.5367431640625e-07f * (am[q] + rm + 1.0f);   // 2^-20
+            }
         }
     }
     __syncthreads();
@@ -238,10 +263,9 @@ __global__ __launch_bounds__(256) void sps_detect_kernel(
                      v > m[-1] && v >= m[1] && v >= m[kHaloCols - 1] && v >= m[kHaloCols] && v >= m[kHaloCols + 1];
                 if (best_out) best_out[static_cast<int64_t>(d) * best_pitch + (t - t_begin)] = static_cast<float>(v);
             } else {
-                const int64_t* cen = reinterpret_cast<const int64_t*>(best);
-                const float* b32 = reinterpret_cast<const float*>(cen + kHaloRows * kMaxWidths) + 2 * kHaloRows * kMaxWidths;
-                const float* e32 = b32 + kHaloRows * kHaloCols;
-                const int ci = (ri + 1) * kHaloCols + (tc + 1);
+                const float* b32 = reinterpret_cast<const float*>(best) + 3 * kHaloRows * kMaxWidths + kHaloRows;
+                const float* e32 = b32 + kSpsRows * kSpsTile;
+                const int ci = ri * kSpsTile + tc;
                 if (b32[ci] >= static_cast<float>(threshold) - e32[ci]) {
                     auto val = [&](int r, int c) {
                         const int dr = d0 - 1 + r;
@@ -395,7 +419,9 @@ int launch_single_pulse(const aa_plan_s* p, const int32_t* d_dd, int64_t dd_pitc
     const int tw = kSpsTile + 1 + p->wmax;
     const size_t lds = kBestBytes + sizeof(double) * (kHaloRows * 2 * kMaxWidths) + sizeof(uint32_t) * kHaloRows * (tw + 1);
     const unsigned rowblocks = static_cast<unsigned>((p->ndm + kSpsRows - 1) / kSpsRows);
-    hipLaunchKernelGGL(d_best ? sps_detect_kernel<true> : sps_detect_kernel<false>,
+    // the float32 screen needs every window sum below 2^31 (int32 centred sums)
+    const bool screen = !d_best && static_cast<uint64_t>(p->nchan) * 255u * static_cast<uint64_t>(p->wmax) < (1ull << 31);
+    hipLaunchKernelGGL(screen ? sps_detect_kernel<false> : sps_detect_kernel<true>,
                        dim3(static_cast<unsigned>(L.ntiles), rowblocks), dim3(256), lds, stream,
                        d_dd, dd_pitch, dd_t0, dd_n, t_begin, t_end, t_total, p->stat_block, p->ndm,
                        static_cast<double>(p->threshold), sc, norms, rowcount, mask, L.nwords, d_best, best_pitch);
