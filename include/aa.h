@@ -124,7 +124,8 @@ int aa_dedisperse(aa_plan_t plan, const uint8_t* d_in, int64_t in_pitch, int64_t
  * and must not run concurrently with compute calls on the same plan.
  *   aa_variant_count()            number of variants
  *   aa_variant_info(v, out)       shape of variant v
- *   aa_plan_set_variant(plan, v)  prepare v and use it for aa_dedisperse
+ *   aa_plan_set_variant(plan, v)  prepare v and use it for aa_dedisperse (a new plan uses
+ *                                 variant 12, the 16-wave i8 matrix-core kernel)
  *   aa_plan_get_variant(plan, v)  variant in use
  *   aa_autotune(...)              time every variant on the caller's buffers (reps runs
  *                                 each, HIP events on `stream`), select the fastest,

@@ -69,7 +69,7 @@ constexpr int mfma_lds_bytes(int tile, int depth) { return tile * 32 * 4 + depth
 //   [224, 228)  i32 max e over the channel block's trials
 constexpr int kRecE = 128, kRecPhase = 192, kRecTiles = 196, kRecLeft = 200, kRecNextNeed = 204, kRecNextRs = 208, kRecMaxE = 224;
 extern const DedispVariant kDedispVariants[kNumDedispVariants];
-constexpr int kDefaultDedispVariant = 0;
+constexpr int kDefaultDedispVariant = 12;   // i8 matrix cores, 16 waves
 
 // Single-pulse-search tiling: a work-group covers kSpsRows DM rows and kSpsTile starts.
 constexpr int kSpsTile = 256;
