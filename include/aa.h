@@ -249,19 +249,26 @@ int aa_batch_run(const aa_batch_beam_t* beams, int32_t nbeams, int32_t variant, 
  * Requests queue on the host. A scheduler thread admits them in arrival order, and
  * in order per beam, when arena memory and a result slot are free. Chunks of
  * different beams therefore overlap on the GPU. aa_poll returns finished chunks.
- * h_chunk must be pinned (hipHostMalloc, or torch pin_memory) and stay untouched
- * until its tag has been returned by aa_poll. submit, poll and release are
- * thread-safe. destroy drains all work in flight.
+ * h_chunk must stay untouched until its tag has been returned by aa_poll. Pinned
+ * memory (hipHostMalloc, or torch pin_memory) takes the fast paths below. Pageable
+ * memory also works: by default the runtime stages each copy itself (slow, and the
+ * copies stop overlapping); with AA_PIPE_STAGED the pipeline stages it through a ring
+ * of small pinned bounce buffers (2 * nstreams of about nchan * max_chunk / nstreams
+ * bytes, pinned when a beam is added), filled by one host thread per compute stream;
+ * the scheduler performs those host copies, so submit and poll calls may wait for
+ * them. submit, poll and release are thread-safe. destroy drains all work in flight.
  * H2D: when h_chunk, pitch and the destination column are 16-byte aligned, a row-gather
  * kernel reads the mapped pinned rows directly. Otherwise, or with AA_PIPE_SDMA_COPY,
  * hipMemcpy2DAsync is used.
  * Flags: AA_PIPE_SERIAL puts copies and kernels on one stream, with no overlap (the
  * plain single-stream baseline). AA_PIPE_TIMING records HIP-event times for copies
- * and kernels; aa_pipeline_stats reports them.
+ * and kernels; aa_pipeline_stats reports them. AA_PIPE_STAGED: staged pageable
+ * input, as above (section 2's pinned bounce buffers and per-stream host threads).
  */
 #define AA_PIPE_SERIAL 1u
 #define AA_PIPE_TIMING 2u
 #define AA_PIPE_SDMA_COPY 4u
+#define AA_PIPE_STAGED 8u
 #define AA_SUBMIT_LAST 1u
 
 typedef struct aa_pipeline_s* aa_pipeline_t;
@@ -273,7 +280,7 @@ typedef struct {
     int32_t  cand_cap;      /* candidate capacity per sub-chunk (0 means 65536)                */
     int32_t  result_slots;  /* sub-chunks in flight at once (0 means 4 * nstreams)            */
     int64_t  hbm_budget;    /* arena bytes (0: size for one chunk per stream + all histories) */
-    uint32_t flags;         /* AA_PIPE_SERIAL | AA_PIPE_TIMING                                 */
+    uint32_t flags;         /* AA_PIPE_SERIAL | AA_PIPE_TIMING | AA_PIPE_SDMA_COPY | AA_PIPE_STAGED */
 } aa_pipeline_opts_t;
 
 typedef struct {

@@ -62,7 +62,7 @@ class PipelineStats(C.Structure):
                 ("kernel_sum_ms", C.c_double)]
 
 
-AA_PIPE_SERIAL, AA_PIPE_TIMING, AA_PIPE_SDMA_COPY, AA_SUBMIT_LAST = 1, 2, 4, 1
+AA_PIPE_SERIAL, AA_PIPE_TIMING, AA_PIPE_SDMA_COPY, AA_PIPE_STAGED, AA_SUBMIT_LAST = 1, 2, 4, 8, 1
 AA_BATCH_STATIC = 1
 
 

@@ -197,18 +197,19 @@ def candidates_as_tuples(arr):
 class Pipeline:
     """aa_pipeline_*: streamed chunks over HIP streams with per-beam device tails.
 
-    submit() takes pinned host memory: a torch uint8 tensor made with pin_memory(), or
-    a numpy view of one. The memory must stay untouched until poll() has returned
-    the chunk's tag.
+    submit() takes host memory as a torch uint8 tensor or a numpy array. Pinned memory
+    (torch pin_memory) takes the fast copy paths; pageable memory is staged by the
+    runtime, or by the pipeline's pinned bounce buffers when staged=True. The memory
+    must stay untouched until poll() has returned the chunk's tag.
     """
 
     def __init__(self, nstreams=4, max_beams=1, max_chunk=1 << 18, cand_cap=1 << 14, result_slots=0,
-                 hbm_budget=8 << 30, serial=False, timing=False, sdma_copy=False):
+                 hbm_budget=8 << 30, serial=False, timing=False, sdma_copy=False, staged=False):
         o = N.PipelineOpts()
         o.nstreams, o.max_beams, o.max_chunk = int(nstreams), int(max_beams), int(max_chunk)
         o.cand_cap, o.result_slots, o.hbm_budget = int(cand_cap), int(result_slots), int(hbm_budget)
         o.flags = ((N.AA_PIPE_SERIAL if serial else 0) | (N.AA_PIPE_TIMING if timing else 0)
-                   | (N.AA_PIPE_SDMA_COPY if sdma_copy else 0))
+                   | (N.AA_PIPE_SDMA_COPY if sdma_copy else 0) | (N.AA_PIPE_STAGED if staged else 0))
         h = C.c_void_p()
         N.check(N.lib().aa_pipeline_create(C.byref(o), C.byref(h)))
         self._h = h
@@ -222,7 +223,9 @@ class Pipeline:
         return b.value
 
     def submit(self, beam, host, nsamp=None, tag=0, last=False, pitch=None):
-        """host: pinned uint8 [nchan, pitch] (torch tensor or numpy view of one)."""
+        """host: uint8 [nchan, pitch], a torch tensor or a numpy array. Pinned memory takes
+        the fast copy paths; pageable memory is staged by the runtime, or by the pipeline's
+        bounce buffers when it was created with staged=True."""
         if hasattr(host, "data_ptr"):
             ptr, rows, cols, rp = host.data_ptr(), host.shape[0], host.shape[1], host.stride(0)
         else:

@@ -14,11 +14,17 @@
 //    issues copies and kernels, polls events (hipEventQuery, never blocking), and
 //    completes results. The atomics in the search kernels are stream-private
 //    counters, so no wait here depends on another stream's atomics.
+//  * Staged pageable input (AA_PIPE_STAGED, the paper's section 2 remedy for pageable
+//    buffers): a ring of small pinned bounce buffers, allocated when a beam is added,
+//    is filled by host-to-host copies split over one host thread per compute stream,
+//    and each filled buffer is copied to the device like pinned input. A bounce
+//    buffer is refilled only after the event of its previous device copy.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <thread>
@@ -66,6 +72,72 @@ struct Request {
     size_t pending = 0;
 };
 
+// Fork-join pool of host threads for the staging copies: run(n, fn) calls fn(i) for
+// i < n, spread over the pool and the calling thread, and returns when all are done.
+class StagePool {
+  public:
+    void start(int nthreads) {
+        for (int i = 0; i < nthreads; ++i) th_.emplace_back([this] { loop(); });
+    }
+    ~StagePool() {
+        {
+            std::lock_guard<std::mutex> g(m_);
+            quit_ = true;
+        }
+        cv_.notify_all();
+        for (auto& t : th_) t.join();
+    }
+    template <class F>
+    void run(int n, F fn) {
+        if (th_.empty() || n <= 1) {
+            for (int i = 0; i < n; ++i) fn(i);
+            return;
+        }
+        std::unique_lock<std::mutex> lk(m_);
+        job_ = fn;
+        next_ = 0;
+        total_ = n;
+        left_ = n;
+        ++gen_;
+        cv_.notify_all();
+        while (next_ < total_) {          // the caller works too
+            const int i = next_++;
+            lk.unlock();
+            fn(i);
+            lk.lock();
+            --left_;
+        }
+        done_cv_.wait(lk, [&] { return left_ == 0; });
+        job_ = nullptr;
+    }
+
+  private:
+    void loop() {
+        std::unique_lock<std::mutex> lk(m_);
+        uint64_t seen = 0;
+        for (;;) {
+            cv_.wait(lk, [&] { return quit_ || (gen_ != seen && next_ < total_); });
+            if (quit_) return;
+            while (next_ < total_) {
+                const int i = next_++;
+                auto fn = job_;
+                lk.unlock();
+                fn(i);
+                lk.lock();
+                if (--left_ == 0) done_cv_.notify_all();
+            }
+            seen = gen_;
+        }
+    }
+    std::vector<std::thread> th_;
+    std::mutex m_;
+    std::condition_variable cv_, done_cv_;
+    std::function<void(int)> job_;
+    int next_ = 0, total_ = 0, left_ = 0;
+    uint64_t gen_ = 0;
+    bool quit_ = false;
+};
+
 struct Beam {
     aa_plan_t plan = nullptr;
     int64_t pitch = 0, cols = 0;
@@ -111,6 +183,14 @@ struct aa_pipeline_s {
     bool started = false;
     std::thread thr;
     std::string thread_error;
+    // staged pageable input
+    std::vector<uint8_t*> bounce;
+    std::vector<hipEvent_t> bounce_ev;
+    size_t bounce_bytes = 0;
+    unsigned bounce_next = 0;
+    StagePool stagers;
+    bool staged() const { return opt.flags & AA_PIPE_STAGED; }
+    int grow_bounce(size_t bytes);
 
     hipEvent_t get_event(bool timing) {
         auto& pool = timing ? tev_pool : ev_pool;
@@ -199,14 +279,49 @@ bool aa_pipeline_s::try_issue(Request* r) {
         else
             (void)hipGetLastError();
     }
+    if (staged()) hdev = nullptr;   // pageable input: copied through the bounce buffers
     const int npc = std::max<int>(1, std::min<int>(opt.nstreams, static_cast<int>((r->n + 4095) / 4096)));
+    if (staged() && r->n > 0) {
+        // the widest piece the loop below can cut, against the bounce size set at add_beam
+        const int64_t widest = (r->n + npc - 1) / npc + 15 * (npc - 1);
+        if (static_cast<size_t>((widest + 15) & ~int64_t{15}) * static_cast<size_t>(nchan) > bounce_bytes) {
+            r->status = fail(AA_EINVAL, "aa_stream_submit: staged piece exceeds the bounce buffers");
+            for (size_t j = 0; j < pieces.size(); ++j) arena.release(offs[j], need[j]);
+            return true;
+        }
+    }
     std::vector<hipEvent_t> pev;
     std::vector<int64_t> pend;   // end column (exclusive) covered after piece i
     for (int i = 0; i < npc; ++i) {
         int64_t w = (r->n - src) / (npc - i);
         if (i + 1 < npc) w &= ~int64_t{15};
         else w = r->n - src;
-        if (w > 0) {
+        if (w > 0 && staged()) {
+            // host-to-host into a pinned bounce buffer (rows split over the stage threads),
+            // then the device copy from it; the buffer's previous copy must have finished
+            const unsigned j = bounce_next++ % static_cast<unsigned>(bounce.size());
+            if (bounce_ev[j]) (void)hipEventSynchronize(bounce_ev[j]);
+            const int64_t bp = (w + 15) & ~int64_t{15};   // bp * nchan <= bounce_bytes, checked above
+            uint8_t* hb = bounce[j];
+            const uint8_t* hs = r->h + src;
+            const int64_t sp = r->pitch;
+            const int parts = std::min<int>(opt.nstreams, static_cast<int>(nchan));
+            stagers.run(parts, [&](int q) {
+                const int64_t c0 = nchan * q / parts, c1 = nchan * (q + 1) / parts;
+                for (int64_t c = c0; c < c1; ++c) std::memcpy(hb + c * bp, hs + c * sp, static_cast<size_t>(w));
+            });
+            void* dp = nullptr;
+            const bool mapped = hipHostGetDevicePointer(&dp, hb, 0) == hipSuccess && dp;
+            if (!mapped) (void)hipGetLastError();
+            const int64_t body = (mapped && (col & 15) == 0 && (bm.pitch & 15) == 0) ? (w & ~int64_t{15}) : 0;
+            if (body)
+                (void)launch_gather_rows(bm.buf[nb] + col, bm.pitch, static_cast<const uint8_t*>(dp), bp, body, nchan, cs);
+            if (w > body)
+                (void)hipMemcpy2DAsync(bm.buf[nb] + col + body, bm.pitch, hb + body, bp, w - body, nchan,
+                                       hipMemcpyHostToDevice, cs);
+            if (!bounce_ev[j]) bounce_ev[j] = get_event(false);
+            (void)hipEventRecord(bounce_ev[j], cs);
+        } else if (w > 0) {
             if (hdev && (w & 15) == 0)
                 (void)launch_gather_rows(bm.buf[nb] + col, bm.pitch, hdev + src, r->pitch, w, nchan, cs);
             else if (hdev) {   // 16-byte body by the kernel, ragged tail by the runtime copy
@@ -442,8 +557,34 @@ extern "C" int aa_pipeline_create(const aa_pipeline_opts_t* opts, aa_pipeline_t*
     if (hipEventCreate(&p->ref) != hipSuccess) return cleanup(fail(AA_EHIP, "aa_pipeline_create: event"));
     (void)hipEventRecord(p->ref, p->copy);
     (void)hipEventSynchronize(p->ref);
+    if (o.flags & AA_PIPE_STAGED) p->stagers.start(o.nstreams - 1);
     p->thr = std::thread([p] { p->run(); });
     *out = p;
+    return AA_OK;
+}
+
+// Bounce buffers for staged pageable input: 2 * nstreams pinned buffers of `bytes`
+// (one piece of a chunk each). Plan-time work: waits for copies still using the old
+// buffers before it replaces them.
+int aa_pipeline_s::grow_bounce(size_t bytes) {
+    if (bytes <= bounce_bytes) return AA_OK;
+    for (hipEvent_t e : bounce_ev)
+        if (e) (void)hipEventSynchronize(e);
+    for (uint8_t* b : bounce) (void)hipHostFree(b);
+    bounce.clear();
+    const int n = 2 * opt.nstreams;
+    for (int i = 0; i < n; ++i) {
+        uint8_t* b = nullptr;
+        if (hipHostMalloc(reinterpret_cast<void**>(&b), bytes, hipHostMallocDefault) != hipSuccess) {
+            for (uint8_t* q : bounce) (void)hipHostFree(q);
+            bounce.clear();
+            bounce_bytes = 0;
+            return fail(AA_ENOMEM, "aa_pipeline_add_beam: cannot pin staging buffers");
+        }
+        bounce.push_back(b);
+    }
+    bounce_ev.resize(n, nullptr);
+    bounce_bytes = bytes;
     return AA_OK;
 }
 
@@ -465,6 +606,20 @@ extern "C" int aa_pipeline_add_beam(aa_pipeline_t p, aa_plan_t plan, int32_t* be
     }
     b.buf[0] = p->arena.base + b.off[0];
     b.buf[1] = p->arena.base + b.off[1];
+    if (p->staged()) {
+        // try_issue cuts a chunk of n samples into npc <= nstreams pieces, each but the
+        // last rounded down to 16 columns, so a piece spans at most n / npc + 15 (npc - 1)
+        // columns, with n / npc <= max(ceil(max_chunk / nstreams), 4096); it is packed
+        // with a 16-byte pitch
+        const int64_t piece = std::max<int64_t>((p->opt.max_chunk + p->opt.nstreams - 1) / p->opt.nstreams, 4096) +
+                              16 * static_cast<int64_t>(p->opt.nstreams);
+        const int rc = p->grow_bounce(static_cast<size_t>((piece + 15) & ~int64_t{15}) * plan->nchan);
+        if (rc != AA_OK) {
+            p->arena.release(b.off[0], bytes);
+            p->arena.release(b.off[1], bytes);
+            return rc;
+        }
+    }
     p->beams.push_back(b);
     *beam = static_cast<int32_t>(p->beams.size() - 1);
     return AA_OK;
@@ -617,6 +772,9 @@ extern "C" int aa_pipeline_destroy(aa_pipeline_t p) {
     for (hipStream_t s : p->comp) (void)hipStreamDestroy(s);
     (void)hipFree(p->d_arena);
     (void)hipHostFree(p->h_slots);
+    for (hipEvent_t e : p->bounce_ev)
+        if (e) (void)hipEventDestroy(e);
+    for (uint8_t* b : p->bounce) (void)hipHostFree(b);
     delete p;
     return AA_OK;
 }

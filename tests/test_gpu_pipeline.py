@@ -32,20 +32,21 @@ def sig():
     x = _signal(nchan, nsamp, seed=31)
     want = oracle.run(x, nsamp, F_TOP, FOFF, TSAMP, dms, WIDTHS, 6.0, stat_block=32768)["candidates"]
     host = torch.from_numpy(np.ascontiguousarray(x)).pin_memory()
-    return dict(x=x, host=host, nchan=nchan, nsamp=nsamp, dms=dms, want=want)
+    return dict(x=x, host=host, pageable=np.ascontiguousarray(x), nchan=nchan, nsamp=nsamp, dms=dms, want=want)
 
 
-def _run(sig, chunk, nstreams, serial=False, cap=1 << 14, sdma=False):
+def _run(sig, chunk, nstreams, serial=False, cap=1 << 14, sdma=False, staged=False, pageable=False):
     from paper_2101_00941_amd import Pipeline, Plan
     plan = Plan(sig["nchan"], sig["nsamp"], F_TOP, FOFF, TSAMP, sig["dms"], WIDTHS, 6.0, 32768)
     pipe = Pipeline(nstreams=nstreams, max_beams=1, max_chunk=chunk, cand_cap=cap, hbm_budget=2 << 30,
-                    serial=serial, timing=True, sdma_copy=sdma)
+                    serial=serial, timing=True, sdma_copy=sdma, staged=staged)
     b = pipe.add_beam(plan)
-    host, nsamp = sig["host"], sig["nsamp"]
+    host, nsamp = (sig["pageable"] if pageable else sig["host"]), sig["nsamp"]
     tags = []
     for k, a in enumerate(range(0, nsamp, chunk)):
         n = min(chunk, nsamp - a)
-        pipe.submit(b, host[:, a:a + n], nsamp=n, pitch=host.stride(0), tag=k, last=(a + n == nsamp))
+        pitch = host.strides[0] if pageable else host.stride(0)
+        pipe.submit(b, host[:, a:a + n], nsamp=n, pitch=pitch, tag=k, last=(a + n == nsamp))
         tags.append(k)
     got, seen, covered = [], set(), []
     while len(seen) < len(tags):
@@ -86,6 +87,17 @@ def test_odd_chunk_sizes(sig, chunk):
 def test_runtime_copy_path_matches(sig):
     got, _, _ = _run(sig, 1 << 17, 2, sdma=True)
     assert_candidates_equal(got, sig["want"])
+
+
+@pytest.mark.parametrize("nstreams,chunk,staged", [(1, 1 << 17, False), (4, 1 << 17, True), (3, 99_999, True),
+                                                   (8, 40_000, True)])
+def test_pageable_input_matches(sig, nstreams, chunk, staged):
+    """Pageable host input: staged through the runtime, or through the pipeline's pinned
+    bounce buffers and stage threads; the result equals the whole-signal oracle."""
+    say(f"pageable input nstreams={nstreams} chunk={chunk} staged={staged}")
+    got, covered, st = _run(sig, chunk, nstreams, staged=staged, pageable=True)
+    assert_candidates_equal(got, sig["want"])
+    assert st["completed"] == st["submitted"]
 
 
 def test_multi_beam_mix_equals_alone():
