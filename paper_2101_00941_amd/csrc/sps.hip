@@ -85,12 +85,21 @@ __global__ __launch_bounds__(256) void sps_stats_kernel(const int32_t* __restric
 // ---- detection ----------------------------------------------------------------
 constexpr int kHaloRows = kSpsRows + 2;
 constexpr int kHaloCols = kSpsTile + 2;
-// LDS region shared by the exact path (float64 best per halo cell) and the float32
-// screen (per row: negated centres, fractions x r, r, max r; per inner cell: best32 and
-// its error bound)
-constexpr int kExactBytes = kHaloRows * kHaloCols * 8;
-constexpr int kScreenBytes = kHaloRows * kMaxWidths * (4 + 4 + 4) + kHaloRows * 4 + kSpsRows * kSpsTile * (4 + 4);
-constexpr int kBestBytes = ((kExactBytes > kScreenBytes ? kExactBytes : kScreenBytes) + 15) / 16 * 16;
+
+// LDS of a detection work-group, in this order: prefix sums [kHaloRows][pw] (u32,
+// pw = kSpsTile + 2 + wmax), the float64 normalisation [kHaloRows][2 nw], then either
+// the float64 best S/N of every halo cell [kHaloRows][kHaloCols] (EXACT) or the screen
+// constants of the inner rows [kSpsRows][nw] (16 bytes each).
+struct DetectLds {
+    int nrm, tail, total;   // byte offsets
+};
+__host__ __device__ inline DetectLds detect_lds(int wmax, int nw, bool exact) {
+    DetectLds L;
+    L.nrm = (kHaloRows * (kSpsTile + 2 + wmax) * 4 + 15) / 16 * 16;
+    L.tail = L.nrm + kHaloRows * 2 * nw * 8;
+    L.total = L.tail + (exact ? kHaloRows * kHaloCols * 8 : kSpsRows * nw * 16);
+    return L;
+}
 
 // Exact value of one halo cell: best S/N over the widths, float64, same operation order
 // as the oracle. -inf outside the range of rows and starts.
@@ -98,7 +107,7 @@ __device__ __forceinline__ double exact_best(const uint32_t* pre, int pw, const 
                                              int r, int c, bool valid) {
     if (!valid) return -__builtin_huge_val();
     const uint32_t* pr = pre + r * pw + c;
-    const double* nr = nrm + r * 2 * kMaxWidths;
+    const double* nr = nrm + r * 2 * sc.nw;
     double v = 0.0;
     for (int k = 0; k < sc.nw; ++k) {
         const uint32_t s = pr[sc.widths[k]] - pr[0];
@@ -109,12 +118,16 @@ __device__ __forceinline__ double exact_best(const uint32_t* pre, int pw, const 
 }
 
 // EXACT: every halo cell in float64 (needed when the best plane is an output).
-// Otherwise a float32 screen runs first: boxcar sums are centred on the integer nearest
-// w*mu, and the S/N error is bounded by eps = 2^-20 (|S/N| + r + 1), well above the
-// float32 rounding of the centred value, the centre's fraction and r. Only cells with
-// best32 >= threshold - eps are evaluated exactly, together with their 8 neighbours. The
-// peak decision is then the exact float64 rule, and every other cell is certainly below
-// the threshold.
+// Otherwise a float32 screen runs first. Per row and width it uses the integer centre
+// c = rint(w*mu), the fraction f = w*mu - c and r, so that S/N = (S - c - f) r. The
+// centred sum S - c is exact in int32 (the launcher takes this path only when every
+// window sum is below 2^31), and one fma gives the float32 S/N of each width within
+// 1.5 * 2^-23 (|S/N| + r) of the float64 one. For v32, the float32 best over the widths,
+// the float64 best is then below v32 + 2^-20 (|v32| + max_w r + 1): widths with a
+// negative float32 S/N stay below that bound because the error shrinks as the value
+// grows. Only cells that reach the threshold under this bound are evaluated exactly,
+// together with their 8 neighbours. The peak decision is then the exact float64 rule,
+// and every other cell is certainly below the threshold.
 template <bool EXACT>
 __global__ __launch_bounds__(256) void sps_detect_kernel(
     const int32_t* __restrict__ dd, int64_t dd_pitch, int64_t dd_t0, int64_t dd_n, int64_t t_begin,
@@ -122,41 +135,76 @@ __global__ __launch_bounds__(256) void sps_detect_kernel(
     const double* __restrict__ norms, int32_t* __restrict__ rowcount, uint32_t* __restrict__ mask,
     int64_t nwords, float* __restrict__ best_out, int64_t best_pitch) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    const int nw = sc.nw;
     const int tw = kSpsTile + 1 + sc.wmax;            // D columns t_tile0-1 .. t_tile0+255+wmax
     const int pw = tw + 1;                            // prefix entries per row
-    double* best = reinterpret_cast<double*>(smem);                      // kBestBytes, see above
-    double* nrm = reinterpret_cast<double*>(smem + kBestBytes);          // [kHaloRows][2*nw]
-    uint32_t* pre = reinterpret_cast<uint32_t*>(nrm + kHaloRows * 2 * kMaxWidths);  // [kHaloRows][pw]
-    __shared__ int32_t cnt[kSpsRows];
+    const DetectLds L = detect_lds(sc.wmax, nw, EXACT);
+    uint32_t* pre = reinterpret_cast<uint32_t*>(smem);                   // [kHaloRows][pw]
+    double* nrm = reinterpret_cast<double*>(smem + L.nrm);               // [kHaloRows][2 nw]
 
     const int64_t tt0 = t_begin + static_cast<int64_t>(blockIdx.x) * kSpsTile;
     const int64_t tile_end = min(tt0 + kSpsTile, t_end);
     const int d0 = blockIdx.y * kSpsRows;
-    const int j = static_cast<int>((tt0 - t_begin) / B);
+    const int j = static_cast<int>((static_cast<uint64_t>(blockIdx.x) * kSpsTile) / static_cast<uint32_t>(B));
     const int64_t lo = max(tt0 - 1, static_cast<int64_t>(0));
     const int64_t hi = (t_total < 0 || tile_end < t_total) ? tile_end + 1 : tile_end;  // best valid in [lo, hi)
     const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const double* nj = norms + static_cast<int64_t>(j) * ndm * (2 * nw);
 
-    if (tid < kSpsRows) cnt[tid] = 0;
-    for (int i = tid; i < kHaloRows * 2 * sc.nw; i += 256) {
-        const int r = i / (2 * sc.nw), k = i - r * (2 * sc.nw);
-        const int d = d0 - 1 + r;
-        nrm[r * 2 * kMaxWidths + k] = (d >= 0 && d < ndm) ? norms[(static_cast<int64_t>(j) * ndm + d) * (2 * sc.nw) + k] : 0.0;
+    // halo row r (trial d0 - 1 + r) belongs to wave r % 4: its normalisation and its D
+    // columns, pre[r][1 + i] = D[t_tile0 - 1 + i], lanes over columns (coalesced)
+    {
+        const int64_t col0 = tt0 - 1 - dd_t0;          // plane column of i = 0
+        const int ilo = col0 < 0 ? static_cast<int>(-col0) : 0;
+        const int ihi = static_cast<int>(min<int64_t>(tw, dd_n - col0));
+        for (int r = wave; r < kHaloRows; r += 4) {
+            const int d = d0 - 1 + r;
+            const bool in = d >= 0 && d < ndm;
+            if (lane < 2 * nw) nrm[r * 2 * nw + lane] = in ? nj[static_cast<int64_t>(d) * (2 * nw) + lane] : 0.0;
+            uint32_t* prow = pre + r * pw;
+            if (lane == 0) prow[0] = 0u;
+            if (in) {
+                const int32_t* src = dd + static_cast<int64_t>(d) * dd_pitch + col0;
+                for (int i = lane; i < tw; i += 64) prow[1 + i] = (i >= ilo && i < ihi) ? static_cast<uint32_t>(src[i]) : 0u;
+            } else {
+                for (int i = lane; i < tw; i += 64) prow[1 + i] = 0u;
+            }
+        }
     }
-    // D columns into pre[r][1 + i], i = column t_tile0 - 1 + i
-    for (int i = tid; i < kHaloRows * tw; i += 256) {
-        const int r = i / tw, c = i - r * tw;
-        const int d = d0 - 1 + r;
-        const int64_t col = tt0 - 1 + c - dd_t0;
-        uint32_t v = 0;
-        if (d >= 0 && d < ndm && col >= 0 && col < dd_n) v = static_cast<uint32_t>(dd[static_cast<int64_t>(d) * dd_pitch + col]);
-        pre[r * pw + 1 + c] = v;
+    // screen constants of the inner rows wave + 1 and wave + 5 (lane k holds width k):
+    // {-c, r, -f*r} as int32, float, float, and the row's max r in rm
+    int4* scr = reinterpret_cast<int4*>(smem + L.tail);                  // [kSpsRows][nw]
+    float rm[2] = {0.0f, 0.0f};
+    if constexpr (!EXACT) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int ri = wave + 4 * h;
+            const int d = d0 + ri;
+            float rr = 0.0f;
+            if (lane < nw) {
+                double wmu = 0.0, r64 = 0.0;
+                if (d < ndm) {
+                    wmu = nj[static_cast<int64_t>(d) * (2 * nw) + lane];
+                    r64 = nj[static_cast<int64_t>(d) * (2 * nw) + nw + lane];
+                }
+                const double c = __builtin_rint(wmu);
+                rr = static_cast<float>(r64);
+                int4 q;
+                q.x = -static_cast<int32_t>(c);
+                q.y = __float_as_int(rr);
+                q.z = __float_as_int(-(static_cast<float>(wmu - c) * rr));
+                q.w = 0;
+                scr[ri * nw + lane] = q;
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) rr = fmaxf(rr, __shfl_xor(rr, o, 64));
+            rm[h] = rr;
+        }
     }
-    if (tid < kHaloRows) pre[tid * pw] = 0;
     __syncthreads();
     // inclusive prefix per row, one wave per row, modulo 2^32 (exact window sums < 2^32)
     {
-        const int wave = tid >> 6, lane = tid & 63;
         const int per = (pw + 63) / 64;
         for (int r = wave; r < kHaloRows; r += 4) {
             uint32_t* pr = pre + r * pw;
@@ -178,117 +226,97 @@ __global__ __launch_bounds__(256) void sps_detect_kernel(
     }
     __syncthreads();
     if constexpr (EXACT) {
-        // best S/N over widths for every halo cell
+        double* best = reinterpret_cast<double*>(smem + L.tail);         // [kHaloRows][kHaloCols]
+        __shared__ int32_t cnt[kSpsRows];
+        if (tid < kSpsRows) cnt[tid] = 0;
         for (int i = tid; i < kHaloRows * kHaloCols; i += 256) {
             const int r = i / kHaloCols, c = i - r * kHaloCols;
             const int d = d0 - 1 + r;
             const int64_t t = tt0 - 1 + c;
             best[i] = exact_best(pre, pw, nrm, sc, r, c, d >= 0 && d < ndm && t >= lo && t < hi);
         }
-    } else {
-        // float32 screen of the inner cells. Per row and width: the integer centre
-        // c = rint(w*mu) (negated), f*r with the fraction f = w*mu - c, and r, as floats.
-        // For a start t, dv = S - c is exact in int32 (the launcher takes this path only
-        // when every window sum is below 2^31), x = float(dv) is within 2^-24 |x|, and
-        // snr32 = fma(x, r, -f*r) is within 2^-20 (|S/N| + r + 1) of the float64 S/N.
-        int32_t* ncen = reinterpret_cast<int32_t*>(best);                   // [kHaloRows][kMaxWidths]
-        float* fr = reinterpret_cast<float*>(ncen + kHaloRows * kMaxWidths);
-        float* r32 = fr + kHaloRows * kMaxWidths;
-        float* rmx = r32 + kHaloRows * kMaxWidths;                          // [kHaloRows]
-        float* b32 = rmx + kHaloRows;                                       // [kSpsRows][kSpsTile]
-        float* e32 = b32 + kSpsRows * kSpsTile;
-        for (int i = tid; i < kHaloRows * sc.nw; i += 256) {
-            const int r = i / sc.nw, k = i - r * sc.nw;
-            const double wmu = nrm[r * 2 * kMaxWidths + k];
-            const double c = __builtin_rint(wmu);
-            const float rr = static_cast<float>(nrm[r * 2 * kMaxWidths + sc.nw + k]);
-            ncen[r * kMaxWidths + k] = -static_cast<int32_t>(c);
-            fr[r * kMaxWidths + k] = static_cast<float>(wmu - c) * rr;
-            r32[r * kMaxWidths + k] = rr;
-        }
-        if (tid < kHaloRows) {
-            float m = 0.0f;
-            for (int k = 0; k < sc.nw; ++k) m = fmaxf(m, static_cast<float>(nrm[tid * 2 * kMaxWidths + sc.nw + k]));
-            rmx[tid] = m;
-        }
         __syncthreads();
-        // wave w screens inner rows w and w + 4, lanes run over 4 chunks of 64 starts
-        const int wave = tid >> 6, lane = tid & 63;
-        for (int ri = wave; ri < kSpsRows; ri += 4) {
-            const int r = ri + 1;
-            const uint32_t* pr = pre + r * pw + 1 + lane;   // start tt0 + 64 q + lane
-            uint32_t neg0[4];
-            float v[4], am[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                neg0[q] = 0u - pr[64 * q];
-                v[q] = -__builtin_huge_valf();
-                am[q] = 0.0f;
-            }
-            for (int k = 0; k < sc.nw; ++k) {
-                const int w = sc.widths[k];
-                const uint32_t nc = static_cast<uint32_t>(ncen[r * kMaxWidths + k]);
-                const float rr = r32[r * kMaxWidths + k], nfr = -fr[r * kMaxWidths + k];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int32_t dv = static_cast<int32_t>(pr[64 * q + w] + neg0[q] + nc);
-                    const float snr = __builtin_fmaf(static_cast<float>(dv), rr, nfr);
-                    v[q] = fmaxf(v[q], snr);
-                    am[q] = fmaxf(am[q], fabsf(snr));
-                }
-            }
+        // 3x3 peak test for the inner rows, 64 consecutive starts per wave step
+        for (int item = tid; item < kSpsRows * kSpsTile; item += 256) {
+            const int ri = item / kSpsTile, tc = item - ri * kSpsTile;
             const int d = d0 + ri;
-            const float rm = rmx[r];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int64_t t = tt0 + 64 * q + lane;
-                const bool ok = d < ndm && t >= lo && t < hi;
-                b32[ri * kSpsTile + 64 * q + lane] = ok ? v[q] : -__builtin_huge_valf();
-                e32[ri * kSpsTile + 64 * q + lane] = 9.5367431640625e-07f * (am[q] + rm + 1.0f);   // 2^-20
-            }
-        }
-    }
-    __syncthreads();
-    // 3x3 peak test for the inner rows, 64 consecutive starts per wave step
-    for (int item = tid; item < kSpsRows * kSpsTile; item += 256) {
-        const int ri = item / kSpsTile, tc = item - ri * kSpsTile;
-        const int d = d0 + ri;
-        const int64_t t = tt0 + tc;
-        bool ok = false;
-        if (d < ndm && t < tile_end) {
-            if constexpr (EXACT) {
+            const int64_t t = tt0 + tc;
+            bool ok = false;
+            if (d < ndm && t < tile_end) {
                 const double* m = best + (ri + 1) * kHaloCols + (tc + 1);
                 const double v = m[0];
                 ok = v >= threshold && v > m[-kHaloCols - 1] && v > m[-kHaloCols] && v > m[-kHaloCols + 1] &&
                      v > m[-1] && v >= m[1] && v >= m[kHaloCols - 1] && v >= m[kHaloCols] && v >= m[kHaloCols + 1];
                 if (best_out) best_out[static_cast<int64_t>(d) * best_pitch + (t - t_begin)] = static_cast<float>(v);
-            } else {
-                const float* b32 = reinterpret_cast<const float*>(best) + 3 * kHaloRows * kMaxWidths + kHaloRows;
-                const float* e32 = b32 + kSpsRows * kSpsTile;
-                const int ci = ri * kSpsTile + tc;
-                if (b32[ci] >= static_cast<float>(threshold) - e32[ci]) {
-                    auto val = [&](int r, int c) {
-                        const int dr = d0 - 1 + r;
-                        const int64_t tr = tt0 - 1 + c;
-                        return exact_best(pre, pw, nrm, sc, r, c, dr >= 0 && dr < ndm && tr >= lo && tr < hi);
-                    };
-                    const int r0 = ri + 1, c0 = tc + 1;
-                    const double v = val(r0, c0);
-                    ok = v >= threshold && v > val(r0 - 1, c0 - 1) && v > val(r0 - 1, c0) && v > val(r0 - 1, c0 + 1) &&
-                         v > val(r0, c0 - 1) && v >= val(r0, c0 + 1) && v >= val(r0 + 1, c0 - 1) &&
-                         v >= val(r0 + 1, c0) && v >= val(r0 + 1, c0 + 1);
-                }
+            }
+            const uint64_t bal = __ballot(ok);
+            if (lane == 0 && d < ndm) {
+                const int64_t w = (tt0 - t_begin) / 32 + tc / 32;
+                *reinterpret_cast<uint64_t*>(mask + static_cast<int64_t>(d) * nwords + w) = bal;
+                if (bal) atomicAdd(&cnt[ri], __popcll(bal));
             }
         }
-        const uint64_t bal = __ballot(ok);
-        if ((tid & 63) == 0 && d < ndm) {
-            const int64_t w = (tt0 - t_begin) / 32 + tc / 32;
-            *reinterpret_cast<uint64_t*>(mask + static_cast<int64_t>(d) * nwords + w) = bal;
-            if (bal) atomicAdd(&cnt[ri], __popcll(bal));
+        __syncthreads();
+        if (tid < kSpsRows && d0 + tid < ndm && cnt[tid] > 0) atomicAdd(&rowcount[d0 + tid], cnt[tid]);
+    } else {
+        // wave w screens inner rows w and w + 4; lane l holds starts 64 q + l, q < 4.
+        // The same lanes take the exact peak test of the cells that pass, so each row's
+        // mask words and count come from one wave.
+        const float thr = static_cast<float>(threshold);
+#pragma unroll 1
+        for (int h = 0; h < 2; ++h) {
+            const int ri = wave + 4 * h, r = ri + 1;
+            const int d = d0 + ri;
+            if (d >= ndm) break;
+            const uint32_t* pr = pre + r * pw + 1 + lane;   // prefix at start tt0 + 64 q + lane
+            const int4* sk = scr + ri * nw;
+            uint32_t neg0[4];
+            float v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                neg0[q] = 0u - pr[64 * q];
+                v[q] = -__builtin_huge_valf();
+            }
+            for (int k = 0; k < nw; ++k) {
+                const int w = sc.widths[k];
+                const int4 c = sk[k];
+                const float rr = __int_as_float(c.y), nfr = __int_as_float(c.z);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int32_t dv = static_cast<int32_t>(pr[64 * q + w] + neg0[q] + static_cast<uint32_t>(c.x));
+                    v[q] = fmaxf(v[q], __builtin_fmaf(static_cast<float>(dv), rr, nfr));
+                }
+            }
+            const float slack = rm[h] + 1.0f;
+            uint32_t pass = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (tt0 + 64 * q + lane < tile_end && v[q] + 9.5367431640625e-07f * (fabsf(v[q]) + slack) >= thr)   // 2^-20
+                    pass |= 1u << q;
+            int pop = 0;
+#pragma unroll 1
+            for (int q = 0; q < 4; ++q) {
+                bool ok = false;
+                if ((pass >> q) & 1u) {
+                    auto val = [&](int rr_, int cc) {
+                        const int dr = d0 - 1 + rr_;
+                        const int64_t tr = tt0 - 1 + cc;
+                        return exact_best(pre, pw, nrm, sc, rr_, cc, dr >= 0 && dr < ndm && tr >= lo && tr < hi);
+                    };
+                    const int c0 = 64 * q + lane + 1;
+                    const double x = val(r, c0);
+                    ok = x >= threshold && x > val(r - 1, c0 - 1) && x > val(r - 1, c0) && x > val(r - 1, c0 + 1) &&
+                         x > val(r, c0 - 1) && x >= val(r, c0 + 1) && x >= val(r + 1, c0 - 1) &&
+                         x >= val(r + 1, c0) && x >= val(r + 1, c0 + 1);
+                }
+                const uint64_t bal = __ballot(ok);
+                if (lane == 0)
+                    *reinterpret_cast<uint64_t*>(mask + static_cast<int64_t>(d) * nwords + (tt0 - t_begin) / 32 + 2 * q) = bal;
+                pop += __popcll(bal);
+            }
+            if (lane == 0 && pop > 0) atomicAdd(&rowcount[d], pop);
         }
     }
-    __syncthreads();
-    if (tid < kSpsRows && d0 + tid < ndm && cnt[tid] > 0) atomicAdd(&rowcount[d0 + tid], cnt[tid]);
 }
 
 // ---- emission -------------------------------------------------------------------
@@ -416,11 +444,10 @@ int launch_single_pulse(const aa_plan_s* p, const int32_t* d_dd, int64_t dd_pitc
     hipLaunchKernelGGL(sps_stats_kernel, dim3(static_cast<unsigned>(L.nblk), static_cast<unsigned>(p->ndm)), dim3(256),
                        0, stream, d_dd, dd_pitch, dd_t0, t_begin, t_end, p->stat_block, p->ndm, sc, norms, rowcount);
     AA_HIP(hipGetLastError());
-    const int tw = kSpsTile + 1 + p->wmax;
-    const size_t lds = kBestBytes + sizeof(double) * (kHaloRows * 2 * kMaxWidths) + sizeof(uint32_t) * kHaloRows * (tw + 1);
     const unsigned rowblocks = static_cast<unsigned>((p->ndm + kSpsRows - 1) / kSpsRows);
     // the float32 screen needs every window sum below 2^31 (int32 centred sums)
     const bool screen = !d_best && static_cast<uint64_t>(p->nchan) * 255u * static_cast<uint64_t>(p->wmax) < (1ull << 31);
+    const size_t lds = static_cast<size_t>(detect_lds(p->wmax, p->nwidths, !screen).total);
     hipLaunchKernelGGL(screen ? sps_detect_kernel<false> : sps_detect_kernel<true>,
                        dim3(static_cast<unsigned>(L.ntiles), rowblocks), dim3(256), lds, stream,
                        d_dd, dd_pitch, dd_t0, dd_n, t_begin, t_end, t_total, p->stat_block, p->ndm,
