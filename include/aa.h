@@ -142,6 +142,8 @@ typedef struct {
                          4: i8 matrix-core contraction over an exact split of the shift table */
     int32_t time_tile;   /* output samples per work-group */
     int32_t depth;       /* staging buffers per work-group (loads run depth - 1 passes ahead) */
+    int32_t max_tiles;   /* layout 4: a channel block spans at most 32 * max_tiles rows of the
+                            shifted time axis (31 or 63); 0 for the other layouts */
 } aa_variant_t;
 
 int aa_variant_count(void);

@@ -39,7 +39,7 @@ class PlanInfo(C.Structure):
 class VariantInfo(C.Structure):
     _fields_ = [("id", C.c_int32), ("waves", C.c_int32), ("dm_per_wave", C.c_int32),
                 ("trials_per_block", C.c_int32), ("lds_bytes", C.c_int32), ("layout", C.c_int32),
-                ("time_tile", C.c_int32), ("depth", C.c_int32)]
+                ("time_tile", C.c_int32), ("depth", C.c_int32), ("max_tiles", C.c_int32)]
 
 
 class PipelineOpts(C.Structure):

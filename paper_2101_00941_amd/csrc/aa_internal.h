@@ -40,8 +40,9 @@ struct DedispVariant {
                      // 4: matrix-core contraction (v_mfma_i32_32x32x32_i8), see below
     int tile;        // output samples per work-group (time tile)
     int depth;       // staging buffers in the LDS ring (loads run depth - 1 steps ahead)
+    int max_tiles;   // layout 4: a channel block spans at most 32 * max_tiles rows of t' (31 or 63)
 };
-constexpr int kNumDedispVariants = 14;
+constexpr int kNumDedispVariants = 17;
 
 // Matrix-core variant (layout 4). Within a block of up to 32 trials (first trial d0)
 // and a run of channels, the shift splits exactly as
@@ -52,12 +53,15 @@ constexpr int kNumDedispVariants = 14;
 // matrix B[(c, r)][d] = (r == r[d][c]). D[d][t] receives P[t + E[d]][d]. One
 // MFMA step contracts 4 channels x 8 residuals. A channel block ends where the
 // residual range of the next 4 channels would reach 8.
-constexpr int kMfmaMaxTiles = 63;       // rows of t' per channel block <= 63 * 32
-constexpr int kMfmaRow = 2048;          // staged bytes per channel row
+// A channel block spans at most 32 * max_tiles rows of t', with max_tiles 63 or 31. A
+// staged row then needs at most 32 * max_tiles + 26 bytes: 2048 or 1024 bytes of LDS.
 constexpr int kMfmaRec = 256;           // per-step table record (bytes)
+constexpr int mfma_row_bytes(int max_tiles) { return max_tiles <= 31 ? 1024 : 2048; }
 // LDS of a work-group: int32 accumulator tile [tile][32], then `depth` staging
 // buffers of 4 rows, then `depth` records.
-constexpr int mfma_lds_bytes(int tile, int depth) { return tile * 32 * 4 + depth * (4 * kMfmaRow + kMfmaRec); }
+constexpr int mfma_lds_bytes(int tile, int depth, int max_tiles) {
+    return tile * 32 * 4 + depth * (4 * mfma_row_bytes(max_tiles) + kMfmaRec);
+}
 // Record layout (one per DM block and 4-channel step k; D = the variant's depth):
 //   [0, 128)    u8  8*r[d][4k+i] at 4d+i (d < 32, i < 4)
 //   [128, 192)  i16 e[d] = E[d] - min E of the channel block holding step k
@@ -78,8 +82,9 @@ constexpr int kSpsRows = 8;
 struct DmBlock {
     int32_t first;   // first DM trial of the block
     int32_t count;   // trials in the block (<= waves * dpw)
-    int32_t row;     // LDS row length (bytes) the block needs, multiple of 16
-    int32_t pad;
+    int32_t row;     // LDS row length (bytes) the block needs, multiple of 16 (layouts 0-3)
+    int32_t rs_lo;   // layout 4: smallest and largest staged-row start over the block's
+    int32_t rs_hi;   // channels, relative to the time tile (0 for the other layouts)
 };
 
 // Per-variant tables. For block b and channel c:
@@ -138,7 +143,7 @@ namespace aa {
 int prepare_variant(aa_plan_s* p, int variant);
 // Host tables of the matrix-core variant: DM blocks, 16-aligned staged-row starts
 // [nblk][nchan4] and the per-step records [nblk][nchan4 / 4][kMfmaRec].
-int build_mfma_tables(const aa_plan_s* p, int tile, int depth, std::vector<DmBlock>& blocks,
+int build_mfma_tables(const aa_plan_s* p, int tile, int depth, int max_tiles, std::vector<DmBlock>& blocks,
                       std::vector<int32_t>& rsv, std::vector<uint8_t>& rec);
 void free_tables(DedispTables& t);
 // Launchers (dedisp.hip, sps.hip). Arguments are validated by the callers.

@@ -345,20 +345,21 @@ __device__ __forceinline__ void wait_vmcnt(int n) {
 // of t', columns the 32 trials, and one step contracts 4 channels x 8 residuals.
 // Input bytes enter as x - 128 (signed 8-bit), and 128 * nchan is added back at the end.
 //  * W = 8 or 16 waves. Wave w owns the tiles w + W j of 32 rows of t' (a channel block
-//    needs TILE / 32 to 63 tiles, so a wave owns NT = TILE / (32 W) .. 64 / W of them)
-//    and holds their 32 x 32 int32 accumulators in registers. Each channel block runs a loop specialised
+//    needs TILE / 32 to MAXT tiles, MAXT = 63 or 31, so a wave owns NT = TILE / (32 W)
+//    .. ceil(MAXT / W) of them) and holds their 32 x 32 int32 accumulators in registers. Each channel block runs a loop specialised
 //    for the wave's NT, so the hot loop has no per-tile branches; the loop is bound by
 //    instruction issue, not by the matrix cores.
 //  * At the end of a channel block, each accumulator row t' of trial d is added into
 //    the work-group's [TILE][32] int32 tile in LDS at t = t' - e[d] (ds_add_u32). Lanes
 //    hold 32 distinct trials of one row, so these adds are conflict-free.
-//  * Input rows are staged 4 channels per step, up to 2048 bytes each, by direct
-//    global->LDS loads into a ring of DEPTH buffers, issued DEPTH - 1 steps ahead.
+//  * Input rows are staged 4 channels per step, up to ROW = 2048 (MAXT 63) or 1024
+//    (MAXT 31) bytes each, by direct global->LDS loads into a ring of DEPTH buffers,
+//    issued DEPTH - 1 steps ahead. Each staging wave loads 1024 bytes of one row.
 //    Each step's table record (residuals, e, phases, tile and step counts, and the row
 //    starts and lengths of the step DEPTH - 1 ahead) rides along in the same ring.
-//    Every wave issues exactly one data load per step, and wave 0 also the record, so
-//    waiting until only the newer steps' loads are in flight makes a step's data
-//    complete. Lanes past a row's needed length load a duplicate of its first chunk.
+//    Every staging wave issues exactly one data load per step, and wave 0 also the
+//    record, so waiting until only the newer steps' loads are in flight makes a step's
+//    data complete. Lanes past a row's needed length load a duplicate of its first chunk.
 //  * A lane (row m, half h) reads its two channels' windows as 3 aligned dwords each
 //    and aligns them with v_alignbyte_b32. Every staged chunk that a needed byte lives
 //    in is in range; chunks wholly outside [0, n_in16) are clamped to a valid address,
@@ -368,43 +369,64 @@ struct MfmaCtx {
     const uint8_t* recg;   // this DM block's records
     int64_t t0, last16;
     int K4, wave, lane, m, h, row, half, vlane, ps;
+    bool interior;         // every staged row of the tile lies inside [0, n_in16)
 };
 
-template <int TILE, int DEPTH>
+// Where the next step's loads go: `c` is the wave's channel, `rowp` its input row
+// at the time tile (A.in + c * in_pitch + t0) and `recp` the step's record.
+struct MfmaNext {
+    int c;
+    const uint8_t* rowp;
+    const uint8_t* recp;
+    __device__ __forceinline__ void advance(int64_t step_bytes) {
+        c += 4;
+        rowp += step_bytes;
+        recp += kMfmaRec;
+    }
+};
+
+template <int TILE, int DEPTH, int MAXT>
 struct MfmaLayout {
-    static constexpr int STAGE = 4 * kMfmaRow;
+    static constexpr int ROW = mfma_row_bytes(MAXT);  // staged bytes per channel row
+    static constexpr int PARTS = ROW / 1024;          // staging waves per row
+    static constexpr int SW = 4 * PARTS;              // staging waves
+    static constexpr int STAGE = 4 * ROW;
     static constexpr int ACC = TILE * 32 * 4;
     static constexpr int RING = ACC;                  // byte offsets into LDS
     static constexpr int RECS = ACC + DEPTH * STAGE;
 };
 
-// Loads of step k into ring slot `slot`: each wave stages half a channel row
-// (16 bytes per lane, `need` chunks of the row), then wave 0 the step's record.
-template <int TILE, int DEPTH>
-__device__ __forceinline__ void mfma_issue(const MfmaCtx& cx, uint8_t* lds, int k, int slot, int rs, int need) {
-    using L = MfmaLayout<TILE, DEPTH>;
+// Loads of step k into ring slot `slot`: each staging wave stages 1024 bytes of a
+// channel row (16 bytes per lane, `need` chunks of the row), then wave 0 the step's
+// record.
+template <int TILE, int DEPTH, int MAXT>
+__device__ __forceinline__ void mfma_issue(const MfmaCtx& cx, uint8_t* lds, const MfmaNext& nx, int slot, int rs,
+                                           int need) {
+    using L = MfmaLayout<TILE, DEPTH, MAXT>;
     const DedispArgs& A = *cx.A;
-    if (cx.wave >= 8) return;                          // waves 0..7 stage the 8 half rows
-    const int c = 4 * k + cx.row;
+    if (cx.wave >= L::SW) return;                      // waves 0 .. SW - 1 stage the rows
     const int v = cx.vlane < need ? cx.vlane : 0;
-    uint8_t* dst = lds + L::RING + slot * L::STAGE + cx.row * kMfmaRow + cx.half * 1024;
-    if (c < A.nchan) {
-        const int64_t first = cx.t0 + rs;               // wave-uniform
-        const int top = need < 64 * cx.half + 64 ? need : 64 * cx.half + 64;
-        const uint8_t* rowp = A.in + static_cast<int64_t>(c) * A.in_pitch;
-        if (first >= 0 && first + 16 * top <= A.n_in16) {
-            __builtin_amdgcn_global_load_lds(rowp + first + 16 * v, (lds_void*)dst, 16, 0, 0);
+    uint8_t* dst = lds + L::RING + slot * L::STAGE + cx.row * L::ROW + cx.half * 1024;
+    if (nx.c < A.nchan) {
+        if (cx.interior) {
+            __builtin_amdgcn_global_load_lds(nx.rowp + rs + 16 * v, (lds_void*)dst, 16, 0, 0);
         } else {
-            int64_t pos = first + 16 * v;
-            pos = pos < 0 ? 0 : (pos > cx.last16 ? cx.last16 : pos);
-            __builtin_amdgcn_global_load_lds(rowp + pos, (lds_void*)dst, 16, 0, 0);
+            const int64_t first = cx.t0 + rs;           // wave-uniform
+            const int top = need < 64 * cx.half + 64 ? need : 64 * cx.half + 64;
+            const uint8_t* row0 = nx.rowp - cx.t0;      // the row at sample 0
+            if (first >= 0 && first + 16 * top <= A.n_in16) {
+                __builtin_amdgcn_global_load_lds(row0 + first + 16 * v, (lds_void*)dst, 16, 0, 0);
+            } else {
+                int64_t pos = first + 16 * v;
+                pos = pos < 0 ? 0 : (pos > cx.last16 ? cx.last16 : pos);
+                __builtin_amdgcn_global_load_lds(row0 + pos, (lds_void*)dst, 16, 0, 0);
+            }
         }
     } else {
         __builtin_amdgcn_global_load_lds(A.pad + 16 * v, (lds_void*)dst, 16, 0, 0);
     }
     if (cx.wave == 0)
-        __builtin_amdgcn_global_load_lds(cx.recg + static_cast<int64_t>(k) * kMfmaRec + 4 * cx.lane,
-                                         (lds_void*)(lds + L::RECS + slot * kMfmaRec), 4, 0, 0);
+        __builtin_amdgcn_global_load_lds(nx.recp + 4 * cx.lane, (lds_void*)(lds + L::RECS + slot * kMfmaRec), 4, 0, 0);
 }
 
 // Wait until step k's loads are complete: the steps k + 1 .. k + DEPTH - 2 may still
@@ -424,11 +446,11 @@ __device__ __forceinline__ void mfma_wait(const MfmaCtx& cx, int k) {
 
 // The steps [k0, k1) of one channel block, with NT tiles for this wave (tiles
 // wave + W j). `slot` is the ring slot of step k0 on entry and of step k1 on exit.
-template <int NT, int W, int TILE, int DEPTH>
-__device__ __forceinline__ void mfma_block(const MfmaCtx& cx, uint8_t* lds, int k0, int k1, int& slot,
-                                           i32x16 (&acc)[64 / W]) {
-    using L = MfmaLayout<TILE, DEPTH>;
-    const int lane_base = L::RING + 2 * cx.h * kMfmaRow + 32 * cx.wave + cx.m;
+template <int NT, int W, int TILE, int DEPTH, int MAXT>
+__device__ __forceinline__ void mfma_block(const MfmaCtx& cx, uint8_t* lds, int k0, int k1, int& slot, MfmaNext& nx,
+                                           int64_t step_bytes, i32x16 (&acc)[(MAXT + W - 1) / W]) {
+    using L = MfmaLayout<TILE, DEPTH, MAXT>;
+    const int lane_base = L::RING + 2 * cx.h * L::ROW + 32 * cx.wave + cx.m;
 #pragma unroll 1
     for (int k = k0; k < k1; ++k) {
         if (k > k0) mfma_wait<DEPTH>(cx, k);
@@ -438,7 +460,8 @@ __device__ __forceinline__ void mfma_block(const MfmaCtx& cx, uint8_t* lds, int 
             const int need = __builtin_amdgcn_readfirstlane(*reinterpret_cast<const int32_t*>(lds + rec + kRecNextNeed));
             const int rs = __builtin_amdgcn_readfirstlane(
                 *reinterpret_cast<const int32_t*>(lds + rec + kRecNextRs + 4 * cx.row));
-            mfma_issue<TILE, DEPTH>(cx, lds, k + DEPTH - 1, slot == 0 ? DEPTH - 1 : slot - 1, rs, need);
+            mfma_issue<TILE, DEPTH, MAXT>(cx, lds, nx, slot == 0 ? DEPTH - 1 : slot - 1, rs, need);
+            nx.advance(step_bytes);
         }
         // one-hot B: lane (trial m, half h) holds channels 2h, 2h+1 of the step
         const uint32_t r32 = *reinterpret_cast<const uint32_t*>(lds + rec + 4 * cx.m);
@@ -449,7 +472,7 @@ __device__ __forceinline__ void mfma_block(const MfmaCtx& cx, uint8_t* lds, int 
                          static_cast<int32_t>(o1 >> 32)};
         // data A: lane (row m, half h) reads 8-byte windows of channels 2h, 2h+1
         const int base = lane_base + slot * L::STAGE;
-        const int a0 = base + static_cast<int>(ph & 0xFFu), a1 = base + kMfmaRow + static_cast<int>(ph >> 8);
+        const int a0 = base + static_cast<int>(ph & 0xFFu), a1 = base + L::ROW + static_cast<int>(ph >> 8);
         const int w0 = a0 & ~3, w1 = a1 & ~3;
         const uint32_t u0 = static_cast<uint32_t>(a0 & 3), u1 = static_cast<uint32_t>(a1 & 3);
         uint32_t x[NT][3], y[NT][3];
@@ -475,14 +498,19 @@ __device__ __forceinline__ void mfma_block(const MfmaCtx& cx, uint8_t* lds, int 
     }
 }
 
-template <int W, int TILE, int DEPTH>
+// Channel-block loop of a wave that owns N tiles (N in [U, TPW]): the hot loop is
+// specialised for N. Other values of n cannot occur and map to the nearest instance.
+template <int N, int U, int TPW>
+constexpr int clamp_nt() { return N < U ? U : (N > TPW ? TPW : N); }
+
+template <int W, int TILE, int DEPTH, int MAXT>
 __device__ __forceinline__ void dedisp_mfma_tile(const DedispArgs& A, int blk, int64_t t0) {
     // wave w owns the tiles w + W j (j < TPW); a channel block has at least TILE / 32
     // tiles, so each wave owns at least U of them
-    constexpr int TPW = 64 / W, U = TILE / (32 * W);
-    using L = MfmaLayout<TILE, DEPTH>;
-    static_assert((W == 8 || W == 16) && TILE % 32 == 0 && U >= 1 && U <= 4 && DEPTH >= 3 && DEPTH <= 13,
-                  "waves / tile / depth");
+    constexpr int TPW = (MAXT + W - 1) / W, U = TILE / (32 * W);
+    using L = MfmaLayout<TILE, DEPTH, MAXT>;
+    static_assert((W == 8 || W == 16) && TILE % 32 == 0 && U >= 1 && U <= TPW && TPW <= 8 && DEPTH >= 3 &&
+                  DEPTH <= 13 && (MAXT == 31 || MAXT == 63) && 32 * MAXT >= TILE, "waves / tile / depth / span");
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     int32_t* acc_lds = reinterpret_cast<int32_t*>(lds);
     MfmaCtx cx;
@@ -496,11 +524,18 @@ __device__ __forceinline__ void dedisp_mfma_tile(const DedispArgs& A, int blk, i
     cx.lane = tid & 63;
     cx.m = cx.lane & 31;
     cx.h = cx.lane >> 5;
-    cx.row = cx.wave >> 1;
-    cx.half = cx.wave & 1;
+    // staging waves: row and 1024-byte part of the row; the others read row 0's entries
+    cx.row = cx.wave < L::SW ? cx.wave / L::PARTS : 0;
+    cx.half = cx.wave < L::SW ? cx.wave % L::PARTS : 0;
     cx.vlane = 64 * cx.half + cx.lane;
-    cx.ps = cx.wave == 0 ? 2 : (cx.wave < 8 ? 1 : 0);  // loads this wave issues per step
+    cx.ps = cx.wave == 0 ? 2 : (cx.wave < L::SW ? 1 : 0);  // loads this wave issues per step
     const int32_t* rsv = A.base + static_cast<int64_t>(blk) * A.nchan_pad;
+    {
+        const DmBlock bk = A.blocks[blk];
+        cx.interior = t0 + bk.rs_lo >= 0 && t0 + bk.rs_hi + L::ROW <= A.n_in16;
+    }
+    const int64_t step_bytes = 4 * A.in_pitch;
+    MfmaNext nx{cx.row, A.in + static_cast<int64_t>(cx.row) * A.in_pitch + t0, cx.recg};
 
     for (int i = tid; i < L::ACC / 16; i += 64 * W) reinterpret_cast<u32x4*>(lds)[i] = u32x4{0u, 0u, 0u, 0u};
     int rs_pro[DEPTH - 1];
@@ -508,8 +543,10 @@ __device__ __forceinline__ void dedisp_mfma_tile(const DedispArgs& A, int blk, i
     for (int j = 0; j < DEPTH - 1; ++j)
         rs_pro[j] = j < cx.K4 ? __builtin_amdgcn_readfirstlane(rsv[4 * j + cx.row]) : 0;
 #pragma unroll
-    for (int j = 0; j < DEPTH - 1; ++j)
-        if (j < cx.K4) mfma_issue<TILE, DEPTH>(cx, lds, j, j, rs_pro[j], kMfmaRow / 16);
+    for (int j = 0; j < DEPTH - 1; ++j) {
+        if (j < cx.K4) mfma_issue<TILE, DEPTH, MAXT>(cx, lds, nx, j, rs_pro[j], L::ROW / 16);
+        nx.advance(step_bytes);
+    }
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
 
     i32x16 acc[TPW];
@@ -524,22 +561,12 @@ __device__ __forceinline__ void dedisp_mfma_tile(const DedispArgs& A, int blk, i
         const int nr = __builtin_amdgcn_readfirstlane(*reinterpret_cast<const int32_t*>(lds + rec0 + kRecTiles));
         const int k1 = k0 + __builtin_amdgcn_readfirstlane(*reinterpret_cast<const int32_t*>(lds + rec0 + kRecLeft));
         const int nt = (nr - cx.wave + W - 1) / W;      // tiles of this wave, U .. TPW
-        if constexpr (W == 8) {
-            switch (nt) {
-                case 8: mfma_block<8, W, TILE, DEPTH>(cx, lds, k0, k1, slot, acc); break;
-                case 7: mfma_block<7, W, TILE, DEPTH>(cx, lds, k0, k1, slot, acc); break;
-                case 6: mfma_block<6, W, TILE, DEPTH>(cx, lds, k0, k1, slot, acc); break;
-                case 5: mfma_block<5, W, TILE, DEPTH>(cx, lds, k0, k1, slot, acc); break;
-                case 4: mfma_block<4, W, TILE, DEPTH>(cx, lds, k0, k1, slot, acc); break;
-                default: mfma_block<U, W, TILE, DEPTH>(cx, lds, k0, k1, slot, acc); break;
-            }
-        } else {
-            switch (nt) {
-                case 4: mfma_block<4, W, TILE, DEPTH>(cx, lds, k0, k1, slot, acc); break;
-                case 3: mfma_block<3, W, TILE, DEPTH>(cx, lds, k0, k1, slot, acc); break;
-                case 2: mfma_block<2, W, TILE, DEPTH>(cx, lds, k0, k1, slot, acc); break;
-                default: mfma_block<U, W, TILE, DEPTH>(cx, lds, k0, k1, slot, acc); break;
-            }
+        switch (nt) {
+#define AA_NT(N) \
+    case N: mfma_block<clamp_nt<N, U, TPW>(), W, TILE, DEPTH, MAXT>(cx, lds, k0, k1, slot, nx, step_bytes, acc); break;
+            AA_NT(8) AA_NT(7) AA_NT(6) AA_NT(5) AA_NT(4) AA_NT(3) AA_NT(2)
+#undef AA_NT
+            default: mfma_block<U, W, TILE, DEPTH, MAXT>(cx, lds, k0, k1, slot, nx, step_bytes, acc); break;
         }
         // flush: accumulator register i of lane (m, h) holds row 8 (i / 4) + 4 h + i % 4
         // of the tile and trial m, which goes to t = row - e[m]. The adds are issued as
@@ -583,8 +610,7 @@ __device__ __forceinline__ void dedisp_mfma_tile(const DedispArgs& A, int blk, i
     const DmBlock b = A.blocks[blk];
     const int32_t corr = 128 * A.nchan;
 #pragma unroll 1
-    for (int it = 0; it < TILE * 32 / 4 / (64 * W); ++it) {
-        const int idx = tid + 64 * W * it;
+    for (int idx = tid; idx < TILE * 8; idx += 64 * W) {   // 4 samples x 1 trial per item
         const int d = idx & 31, tq = idx >> 5;
         int32_t v[4];
 #pragma unroll
@@ -604,11 +630,13 @@ __device__ __forceinline__ void dedisp_mfma_tile(const DedispArgs& A, int blk, i
     }
 }
 
-template <int DPW, int W, int LAYOUT, int TILE = kTimeTile, int DEPTH = 2>
-__global__ __launch_bounds__(64 * W) void dedisp_kernel(DedispArgs a) {
+// WPE: waves per SIMD the register allocation must allow (2 work-groups per CU for the
+// 80 KB matrix-core variants).
+template <int DPW, int W, int LAYOUT, int TILE = kTimeTile, int DEPTH = 2, int MAXT = 63, int WPE = 1>
+__global__ __launch_bounds__(64 * W, WPE) void dedisp_kernel(DedispArgs a) {
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
     if constexpr (LAYOUT == 4)
-        dedisp_mfma_tile<W, TILE, DEPTH>(a, bid % a.nblk, static_cast<int64_t>(bid / a.nblk) * TILE);
+        dedisp_mfma_tile<W, TILE, DEPTH, MAXT>(a, bid % a.nblk, static_cast<int64_t>(bid / a.nblk) * TILE);
     else
         dedisp_tile<DPW, W, LAYOUT>(a, bid % a.nblk, static_cast<int64_t>(bid / a.nblk) * kTimeTile);
 }
@@ -619,8 +647,8 @@ __global__ __launch_bounds__(64 * W) void dedisp_kernel(DedispArgs a) {
 // of the same beam (their input rows overlap). A work-group reads the item index from
 // the counter, finds its beam by binary search over item_begin, and exits when the
 // index passes the total: every work-group reaches that exit.
-template <int DPW, int W, int LAYOUT, int TILE = kTimeTile, int DEPTH = 2>
-__global__ __launch_bounds__(64 * W) void dedisp_batch_kernel(const DedispArgs* __restrict__ args,
+template <int DPW, int W, int LAYOUT, int TILE = kTimeTile, int DEPTH = 2, int MAXT = 63, int WPE = 1>
+__global__ __launch_bounds__(64 * W, WPE) void dedisp_batch_kernel(const DedispArgs* __restrict__ args,
                                                               const int64_t* __restrict__ item_begin, int nbeams,
                                                               int64_t total, unsigned long long* counter) {
     __shared__ int64_t item;
@@ -642,7 +670,7 @@ __global__ __launch_bounds__(64 * W) void dedisp_batch_kernel(const DedispArgs* 
         const DedispArgs a = args[lo];
         const int64_t local = it - item_begin[lo];
         if constexpr (LAYOUT == 4)
-            dedisp_mfma_tile<W, TILE, DEPTH>(a, static_cast<int>(local % a.nblk), (local / a.nblk) * TILE);
+            dedisp_mfma_tile<W, TILE, DEPTH, MAXT>(a, static_cast<int>(local % a.nblk), (local / a.nblk) * TILE);
         else
             dedisp_tile<DPW, W, LAYOUT>(a, static_cast<int>(local % a.nblk), (local / a.nblk) * kTimeTile);
         __syncthreads();   // the next item restages LDS buffer 0
@@ -654,10 +682,12 @@ __global__ void reset_counter_kernel(unsigned long long* c) { *c = 0ull; }
 typedef void (*DedispFn)(DedispArgs);
 typedef void (*DedispBatchFn)(const DedispArgs*, const int64_t*, int, int64_t, unsigned long long*);
 
-// Indexed by DedispVariant::id (tiling.cpp).
+// Indexed by DedispVariant::id (tiling.cpp); layout-4 entries repeat the variant's
+// time tile, depth and channel-block span.
 #define AA_VARIANTS(K)                                                                           \
     K<4, 4, 1>, K<2, 8, 1>, K<4, 8, 1>, K<2, 16, 1>, K<2, 8, 0>, K<4, 4, 0>, K<2, 8, 3>, K<4, 4, 3>, \
-        K<2, 8, 2>, K<4, 8, 2>, K<4, 4, 2>, K<4, 8, 4, 1024, 3>, K<2, 16, 4, 1024, 3>, K<2, 16, 4, 768, 7>
+        K<2, 8, 2>, K<4, 8, 2>, K<4, 4, 2>, K<4, 8, 4, 1024, 3>, K<2, 16, 4, 1024, 3>, K<2, 16, 4, 768, 7>, \
+        K<4, 8, 4, 512, 3, 31, 4>, K<2, 16, 4, 512, 3, 31, 8>, K<4, 8, 4, 480, 4, 31, 4>
 const DedispFn kKernels[kNumDedispVariants] = {AA_VARIANTS(dedisp_kernel)};
 const DedispBatchFn kBatchKernels[kNumDedispVariants] = {AA_VARIANTS(dedisp_batch_kernel)};
 #undef AA_VARIANTS

@@ -11,21 +11,26 @@ namespace aa {
 // LDS budgets are sized so that 3 (52 KB) or 2 (80 KB) work-groups fit in one CU's
 // 160 KB of LDS.
 const DedispVariant kDedispVariants[kNumDedispVariants] = {
-    {0, 4, 4, 53248, 1, kTimeTile, 2},    // 256 threads, 16 trials per block, interleaved lanes
-    {1, 8, 2, 53248, 1, kTimeTile, 2},    // 512 threads, 16 trials per block, interleaved lanes
-    {2, 8, 4, 81920, 1, kTimeTile, 2},    // 512 threads, 32 trials per block, interleaved lanes
-    {3, 16, 2, 81920, 1, kTimeTile, 2},   // 1024 threads, 32 trials per block, interleaved lanes
-    {4, 8, 2, 53248, 0, kTimeTile, 2},    // 512 threads, 16 trials per block, contiguous lanes
-    {5, 4, 4, 53248, 0, kTimeTile, 2},    // 256 threads, 16 trials per block, contiguous lanes
-    {6, 8, 2, 53248, 3, kTimeTile, 2},    // 512 threads, 16 trials per block, contiguous lanes, 16-way switch
-    {7, 4, 4, 53248, 3, kTimeTile, 2},    // 256 threads, 16 trials per block, contiguous lanes, 16-way switch
-    {8, 8, 2, 53248, 2, kTimeTile, 2},    // 512 threads, 16 trials per block, interleaved, equal-offset reuse
-    {9, 8, 4, 81920, 2, kTimeTile, 2},    // 512 threads, 32 trials per block, interleaved, equal-offset reuse
-    {10, 4, 4, 53248, 2, kTimeTile, 2},   // 256 threads, 16 trials per block, interleaved, equal-offset reuse
-    // 32 trials per block, i8 matrix cores; waves, time tile and staging depth vary
-    {11, 8, 4, mfma_lds_bytes(1024, 3), 4, 1024, 3},    // 512 threads, 8 tiles per wave
-    {12, 16, 2, mfma_lds_bytes(1024, 3), 4, 1024, 3},   // 1024 threads, 4 tiles per wave
-    {13, 16, 2, mfma_lds_bytes(768, 7), 4, 768, 7},     // 1024 threads, 4 tiles per wave
+    {0, 4, 4, 53248, 1, kTimeTile, 2, 0},    // 256 threads, 16 trials per block, interleaved lanes
+    {1, 8, 2, 53248, 1, kTimeTile, 2, 0},    // 512 threads, 16 trials per block, interleaved lanes
+    {2, 8, 4, 81920, 1, kTimeTile, 2, 0},    // 512 threads, 32 trials per block, interleaved lanes
+    {3, 16, 2, 81920, 1, kTimeTile, 2, 0},   // 1024 threads, 32 trials per block, interleaved lanes
+    {4, 8, 2, 53248, 0, kTimeTile, 2, 0},    // 512 threads, 16 trials per block, contiguous lanes
+    {5, 4, 4, 53248, 0, kTimeTile, 2, 0},    // 256 threads, 16 trials per block, contiguous lanes
+    {6, 8, 2, 53248, 3, kTimeTile, 2, 0},    // 512 threads, 16 trials per block, contiguous lanes, 16-way switch
+    {7, 4, 4, 53248, 3, kTimeTile, 2, 0},    // 256 threads, 16 trials per block, contiguous lanes, 16-way switch
+    {8, 8, 2, 53248, 2, kTimeTile, 2, 0},    // 512 threads, 16 trials per block, interleaved, equal-offset reuse
+    {9, 8, 4, 81920, 2, kTimeTile, 2, 0},    // 512 threads, 32 trials per block, interleaved, equal-offset reuse
+    {10, 4, 4, 53248, 2, kTimeTile, 2, 0},   // 256 threads, 16 trials per block, interleaved, equal-offset reuse
+    // 32 trials per block, i8 matrix cores; waves, time tile, staging depth and the
+    // channel-block span vary. The kernel table in dedisp.hip repeats these parameters.
+    {11, 8, 4, mfma_lds_bytes(1024, 3, 63), 4, 1024, 3, 63},   // 512 threads, 8 tiles per wave
+    {12, 16, 2, mfma_lds_bytes(1024, 3, 63), 4, 1024, 3, 63},  // 1024 threads, 4 tiles per wave
+    {13, 16, 2, mfma_lds_bytes(768, 7, 63), 4, 768, 7, 63},    // 1024 threads, 4 tiles per wave
+    // two work-groups per CU (LDS <= 80 KB, registers for 4 or 8 waves per SIMD)
+    {14, 8, 4, mfma_lds_bytes(512, 3, 31), 4, 512, 3, 31},     // 512 threads, 4 tiles per wave
+    {15, 16, 2, mfma_lds_bytes(512, 3, 31), 4, 512, 3, 31},    // 1024 threads, 2 tiles per wave
+    {16, 8, 4, mfma_lds_bytes(480, 4, 31), 4, 480, 4, 31},     // 512 threads, 4 tiles per wave
 };
 
 void free_tables(DedispTables& t) {
@@ -49,8 +54,8 @@ int upload(T** dst, const std::vector<T>& src) {
 //  * DM blocks: up to 32 consecutive trials such that every 4-channel step on its own
 //    has a residual range below 8 (so a channel block always holds at least one step)
 //    and, for every channel, the spread of f over the block's trials is at most
-//    (kMfmaMaxTiles * 32 - tile). The spread of E over a channel block is bounded
-//    by that, so a channel block never needs more than kMfmaMaxTiles tiles of t'.
+//    (max_tiles * 32 - tile). The spread of E over a channel block is bounded
+//    by that, so a channel block never needs more than max_tiles tiles of t'.
 //    A single trial always qualifies (f = 0).
 //  * Channel blocks: greedy runs of 4-channel steps whose residual range stays below 8.
 //    E[d] = min over the run of f(d, c), r = f - E, e = E - min E, and the staged row
@@ -58,14 +63,15 @@ int upload(T** dst, const std::vector<T>& src) {
 //  * Padded channels (c >= nchan) are staged from a row of 0x80 bytes, which the kernel
 //    maps to 0, so their residuals are 0. Absent trials of a short block have r = 0,
 //    e = 0 and are not written out.
-int build_mfma_tables(const aa_plan_s* p, int tile, int depth, std::vector<DmBlock>& blocks,
+int build_mfma_tables(const aa_plan_s* p, int tile, int depth, int max_tiles, std::vector<DmBlock>& blocks,
                       std::vector<int32_t>& rsv, std::vector<uint8_t>& rec) {
     const int nchan = p->nchan;
     const int nchan4 = (nchan + 3) & ~3;
     const int K4 = nchan4 / 4;
-    const int spread_max = kMfmaMaxTiles * 32 - tile;
-    if (tile % 32 || tile < 256 || spread_max < 0 || depth < 3)
-        return fail(AA_EINVAL, "matrix-core tiling: bad tile or depth");
+    const int spread_max = max_tiles * 32 - tile;
+    const int row = mfma_row_bytes(max_tiles);
+    if (tile % 32 || tile < 256 || spread_max < 0 || depth < 3 || (max_tiles != 31 && max_tiles != 63))
+        return fail(AA_EINVAL, "matrix-core tiling: bad tile, depth or channel-block span");
     auto S = [&](int d, int c) { return p->shifts[static_cast<size_t>(d) * nchan + c]; };
     blocks.clear();
     std::vector<int32_t> fmin(nchan), fmax(nchan);
@@ -94,7 +100,7 @@ int build_mfma_tables(const aa_plan_s* p, int tile, int depth, std::vector<DmBlo
             }
             ++count;
         }
-        blocks.push_back(DmBlock{d0, count, 0, 0});
+        blocks.push_back(DmBlock{d0, count, 0, 0, 0});
         d0 += count;
     }
     const size_t nblk = blocks.size();
@@ -136,7 +142,7 @@ int build_mfma_tables(const aa_plan_s* p, int tile, int depth, std::vector<DmBlo
                 emax = std::max(emax, lo[i]);
             }
             const int tiles = (emax - emin + tile + 31) / 32;
-            if (tiles > kMfmaMaxTiles) return fail(AA_EINVAL, "matrix-core tiling: channel block spread too large");
+            if (tiles > max_tiles) return fail(AA_EINVAL, "matrix-core tiling: channel block spread too large");
             for (int k = k0; k < k1; ++k) {
                 uint8_t* rk = R + static_cast<size_t>(k) * kMfmaRec;
                 for (int j = 0; j < 4; ++j) {
@@ -160,6 +166,8 @@ int build_mfma_tables(const aa_plan_s* p, int tile, int depth, std::vector<DmBlo
             }
             k0 = k1;
         }
+        blocks[bi].rs_lo = *std::min_element(rsv.begin() + bi * nchan4, rsv.begin() + (bi + 1) * nchan4);
+        blocks[bi].rs_hi = *std::max_element(rsv.begin() + bi * nchan4, rsv.begin() + (bi + 1) * nchan4);
         // row starts and lengths of step k + depth - 1, read by the kernel when it issues
         // that step's loads. A row needs the bytes [0, 32 tiles + phase + 11).
         for (int k = 0; k + depth - 1 < K4; ++k) {
@@ -168,7 +176,7 @@ int build_mfma_tables(const aa_plan_s* p, int tile, int depth, std::vector<DmBlo
             std::memcpy(rk + kRecNextRs, &rsv[bi * nchan4 + 4 * (k + depth - 1)], 16);
             int32_t tiles;
             std::memcpy(&tiles, rn + kRecTiles, 4);
-            const int32_t need = std::min(kMfmaRow / 16, (32 * tiles + 15 + 11 + 15) / 16);
+            const int32_t need = std::min(row / 16, (32 * tiles + 15 + 11 + 15) / 16);
             std::memcpy(rk + kRecNextNeed, &need, 4);
         }
     }
@@ -180,14 +188,14 @@ int prepare_mfma(const aa_plan_s* p, const DedispVariant& V, DedispTables& t) {
     std::vector<DmBlock> blocks;
     std::vector<int32_t> rsv;
     std::vector<uint8_t> rec;
-    const int rc0 = build_mfma_tables(p, V.tile, V.depth, blocks, rsv, rec);
+    const int rc0 = build_mfma_tables(p, V.tile, V.depth, V.max_tiles, blocks, rsv, rec);
     if (rc0 != AA_OK) return rc0;
     t.bd = 32;
     t.nchan_pad = (p->nchan + 3) & ~3;
-    t.max_row = kMfmaRow;
+    t.max_row = mfma_row_bytes(V.max_tiles);
     t.blocks = blocks;
     if (p->device >= 0) {
-        std::vector<uint8_t> pad(kMfmaRow, 0x80);
+        std::vector<uint8_t> pad(t.max_row, 0x80);
         int rc = upload(&t.d_blocks, blocks);
         if (rc == AA_OK) rc = upload(&t.d_base, rsv);
         if (rc == AA_OK) rc = upload(reinterpret_cast<uint8_t**>(&t.d_offs), rec);
@@ -235,7 +243,7 @@ int prepare_variant(aa_plan_s* p, int v) {
             omax = std::max(omax, m);
             ++count;
         }
-        DmBlock b{d, count, kTimeTile + 16 + (omax & ~15), 0};
+        DmBlock b{d, count, kTimeTile + 16 + (omax & ~15), 0, 0};
         if (b.row > row_max) return fail(AA_EINVAL, "dedispersion tiling: a single trial does not fit the LDS row");
         max_row = std::max(max_row, b.row);
         blocks.push_back(b);

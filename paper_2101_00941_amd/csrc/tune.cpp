@@ -75,6 +75,7 @@ extern "C" int aa_variant_info(int32_t v, aa_variant_t* out) {
     out->layout = V.layout;
     out->time_tile = V.tile;
     out->depth = V.depth;
+    out->max_tiles = V.max_tiles;
     return AA_OK;
 }
 

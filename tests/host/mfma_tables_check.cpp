@@ -2,7 +2,7 @@
 // kernel's steps (staging with the same row starts, lengths and clamps, one-hot
 // residual selection, per-block flush at t' - e) over the tables that build_mfma_tables
 // produces, compared with D[d][t] = sum_c X[c][t + s[d][c]] computed directly.
-// Host-only plan: no GPU needed. Usage: mfma_tables_check TILE DEPTH
+// Host-only plan: no GPU needed. Usage: mfma_tables_check TILE DEPTH [MAX_TILES]
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -12,7 +12,7 @@
 
 using namespace aa;
 
-static int TILE = 1024, DEPTH = 3;
+static int TILE = 1024, DEPTH = 3, MAXT = 63;
 static int run_case(int nchan, int nsamp, double ftop, double foff, double tsamp, std::vector<double> dms, unsigned seed,
                     int max_tiles_check = 1 << 30) {
     aa_plan_desc_t d{};
@@ -23,7 +23,8 @@ static int run_case(int nchan, int nsamp, double ftop, double foff, double tsamp
     aa_plan_t p = nullptr;
     if (aa_plan(&d, &p) != AA_OK) { printf("plan failed: %s\n", aa_last_error()); return 1; }
     std::vector<DmBlock> blocks; std::vector<int32_t> rsv; std::vector<uint8_t> rec;
-    if (build_mfma_tables(p, TILE, DEPTH, blocks, rsv, rec) != AA_OK) { printf("tables failed: %s\n", aa_last_error()); return 1; }
+    const int ROW = mfma_row_bytes(MAXT);
+    if (build_mfma_tables(p, TILE, DEPTH, MAXT, blocks, rsv, rec) != AA_OK) { printf("tables failed: %s\n", aa_last_error()); return 1; }
     const int nchan4 = (nchan + 3) & ~3, K4 = nchan4 / 4;
     const int64_t M = p->maxshift, n_out = nsamp - M;
     const int64_t pitch = (nsamp + 255) / 256 * 256;
@@ -48,14 +49,14 @@ static int run_case(int nchan, int nsamp, double ftop, double foff, double tsamp
                 const uint8_t* rk = R + (size_t)k * kMfmaRec;
                 // row starts as the kernel obtains them
                 int rs[4];
-                int need = 128;
+                int need = ROW / 16;
                 for (int i = 0; i < 4; ++i)
                     rs[i] = k < DEPTH - 1 ? rsv[bi * nchan4 + 4 * k + i] : *(const int32_t*)(R + (size_t)(k - DEPTH + 1) * kMfmaRec + kRecNextRs + 4 * i);
                 if (k >= DEPTH - 1) need = *(const int32_t*)(R + (size_t)(k - DEPTH + 1) * kMfmaRec + kRecNextNeed);
                 uint8_t row[4][2048];
                 for (int i = 0; i < 4; ++i) {
                     const int c = 4 * k + i;
-                    for (int v0 = 0; v0 < 128; ++v0) {
+                    for (int v0 = 0; v0 < ROW / 16; ++v0) {
                         const int v = v0 < need ? v0 : 0;
                         int64_t pos = t0 + rs[i] + 16 * v;
                         pos = pos < 0 ? 0 : (pos > n_in16 - 16 ? n_in16 - 16 : pos);
@@ -86,7 +87,7 @@ static int run_case(int nchan, int nsamp, double ftop, double foff, double tsamp
                     if (emax != *(const int32_t*)(rk + kRecMaxE)) { printf("max e mismatch at step %d\n", k); return 1; }
                 }
                 if (nr > maxnr) maxnr = nr;
-                if (nr > 63 || nr < TILE / 32) { printf("bad nr %d\n", nr); return 1; }
+                if (nr > MAXT || nr < TILE / 32) { printf("bad nr %d\n", nr); return 1; }
                 for (int q = 0; q < nr; ++q)
                     for (int mrow = 0; mrow < 32; ++mrow)
                         for (int dd = 0; dd < 32; ++dd) {
@@ -97,7 +98,7 @@ static int run_case(int nchan, int nsamp, double ftop, double foff, double tsamp
                                     const int r = rk[4 * dd + ch] / 8;
                                     const int ph = rk[kRecPhase + ch];
                                     const int P = 32 * q + mrow + ph + r;
-                                    if (P >= 2048) { printf("window past row\n"); return 1; }
+                                    if (P >= ROW) { printf("window past row\n"); return 1; }
                                     s += (int)(int8_t)(row[ch][P] ^ 0x80);   // (x ^ 0x80) as int8 = x - 128
                                 }
                             C[(q * 32 + mrow) * 32 + dd] += s;
@@ -131,7 +132,8 @@ static int run_case(int nchan, int nsamp, double ftop, double foff, double tsamp
 }
 int main(int argc, char** argv) {
     if (argc > 2) { TILE = atoi(argv[1]); DEPTH = atoi(argv[2]); }
-    printf("tile %d depth %d\n", TILE, DEPTH);
+    if (argc > 3) MAXT = atoi(argv[3]);
+    printf("tile %d depth %d max tiles %d\n", TILE, DEPTH, MAXT);
     int rc = 0;
     rc |= run_case(1, 3000, 1400.0, 1.0, 64e-6, {0.0, 10.0, 100.0}, 1);
     rc |= run_case(7, 5003, 1500.0, 3.0, 64e-6, {0, 12.5, 25, 37.5, 50}, 2);
