@@ -499,7 +499,7 @@ __device__ __forceinline__ void mfma_block(const MfmaCtx& cx, uint8_t* lds, int 
 }
 
 // Channel-block loop of a wave that owns N tiles (N in [U, TPW]): the hot loop is
-// specialised for N. Other values of n cannot occur and map to the nearest instance.
+// specialised for N. Other values of n cannot occur; their cases are empty.
 template <int N, int U, int TPW>
 constexpr int clamp_nt() { return N < U ? U : (N > TPW ? TPW : N); }
 
@@ -561,12 +561,18 @@ __device__ __forceinline__ void dedisp_mfma_tile(const DedispArgs& A, int blk, i
         const int nr = __builtin_amdgcn_readfirstlane(*reinterpret_cast<const int32_t*>(lds + rec0 + kRecTiles));
         const int k1 = k0 + __builtin_amdgcn_readfirstlane(*reinterpret_cast<const int32_t*>(lds + rec0 + kRecLeft));
         const int nt = (nr - cx.wave + W - 1) / W;      // tiles of this wave, U .. TPW
+        // one inlined loop per value in [U, TPW] (nt = 1 only reaches the default case)
         switch (nt) {
-#define AA_NT(N) \
-    case N: mfma_block<clamp_nt<N, U, TPW>(), W, TILE, DEPTH, MAXT>(cx, lds, k0, k1, slot, nx, step_bytes, acc); break;
+#define AA_NT(N)                                                                                                  \
+    case N:                                                                                                       \
+        if constexpr (N >= U && N <= TPW)                                                                         \
+            mfma_block<clamp_nt<N, U, TPW>(), W, TILE, DEPTH, MAXT>(cx, lds, k0, k1, slot, nx, step_bytes, acc); \
+        break;
             AA_NT(8) AA_NT(7) AA_NT(6) AA_NT(5) AA_NT(4) AA_NT(3) AA_NT(2)
 #undef AA_NT
-            default: mfma_block<U, W, TILE, DEPTH, MAXT>(cx, lds, k0, k1, slot, nx, step_bytes, acc); break;
+            default:
+                if constexpr (U == 1) mfma_block<1, W, TILE, DEPTH, MAXT>(cx, lds, k0, k1, slot, nx, step_bytes, acc);
+                break;
         }
         // flush: accumulator register i of lane (m, h) holds row 8 (i / 4) + 4 h + i % 4
         // of the tile and trial m, which goes to t = row - e[m]. The adds are issued as

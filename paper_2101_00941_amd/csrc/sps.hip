@@ -32,6 +32,22 @@ struct SpsConst {
     double sqrtw[kMaxWidths];
 };
 
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
+// Inclusive prefix sum over the 64 lanes of a wave (modulo 2^32): shifts by 1, 2, 4 and
+// 8 lanes inside each row of 16, then the last lane of row 0 (and of row 2) is added to
+// row 1 (and 3), and the last lane of row 1 to rows 2 and 3. Lanes whose source falls
+// outside the row, or rows masked off, add 0.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x111, 0xf, 0xf, false));
+    v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x112, 0xf, 0xf, false));
+    v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x114, 0xf, 0xf, false));
+    v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x118, 0xf, 0xf, false));
+    v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x142, 0xa, 0xf, false));
+    v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x143, 0xc, 0xf, false));
+    return v;
+}
+
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -86,16 +102,18 @@ __global__ __launch_bounds__(256) void sps_stats_kernel(const int32_t* __restric
 constexpr int kHaloRows = kSpsRows + 2;
 constexpr int kHaloCols = kSpsTile + 2;
 
-// LDS of a detection work-group, in this order: prefix sums [kHaloRows][pw] (u32,
-// pw = kSpsTile + 2 + wmax), the float64 normalisation [kHaloRows][2 nw], then either
-// the float64 best S/N of every halo cell [kHaloRows][kHaloCols] (EXACT) or the screen
+// LDS of a detection work-group, in this order: 8 bytes, prefix sums [kHaloRows][ps]
+// (u32, row stride ps >= kSpsTile + 2 + wmax, a multiple of 4, so that entry 2 of every
+// row is 16-byte aligned), the float64 normalisation [kHaloRows][2 nw], then either the
+// float64 best S/N of every halo cell [kHaloRows][kHaloCols] (EXACT) or the screen
 // constants of the inner rows [kSpsRows][nw] (16 bytes each).
 struct DetectLds {
     int nrm, tail, total;   // byte offsets
 };
+__host__ __device__ inline int detect_row_stride(int wmax) { return 4 * ((kSpsTile + wmax + 3) / 4 + 1); }
 __host__ __device__ inline DetectLds detect_lds(int wmax, int nw, bool exact) {
     DetectLds L;
-    L.nrm = (kHaloRows * (kSpsTile + 2 + wmax) * 4 + 15) / 16 * 16;
+    L.nrm = (8 + kHaloRows * detect_row_stride(wmax) * 4 + 15) / 16 * 16;
     L.tail = L.nrm + kHaloRows * 2 * nw * 8;
     L.total = L.tail + (exact ? kHaloRows * kHaloCols * 8 : kSpsRows * nw * 16);
     return L;
@@ -103,10 +121,10 @@ __host__ __device__ inline DetectLds detect_lds(int wmax, int nw, bool exact) {
 
 // Exact value of one halo cell: best S/N over the widths, float64, same operation order
 // as the oracle. -inf outside the range of rows and starts.
-__device__ __forceinline__ double exact_best(const uint32_t* pre, int pw, const double* nrm, const SpsConst& sc,
+__device__ __forceinline__ double exact_best(const uint32_t* pre, int stride, const double* nrm, const SpsConst& sc,
                                              int r, int c, bool valid) {
     if (!valid) return -__builtin_huge_val();
-    const uint32_t* pr = pre + r * pw + c;
+    const uint32_t* pr = pre + r * stride + c;
     const double* nr = nrm + r * 2 * sc.nw;
     double v = 0.0;
     for (int k = 0; k < sc.nw; ++k) {
@@ -138,8 +156,9 @@ __global__ __launch_bounds__(256) void sps_detect_kernel(
     const int nw = sc.nw;
     const int tw = kSpsTile + 1 + sc.wmax;            // D columns t_tile0-1 .. t_tile0+255+wmax
     const int pw = tw + 1;                            // prefix entries per row
+    const int ps = detect_row_stride(sc.wmax);        // row stride of the prefix sums
     const DetectLds L = detect_lds(sc.wmax, nw, EXACT);
-    uint32_t* pre = reinterpret_cast<uint32_t*>(smem);                   // [kHaloRows][pw]
+    uint32_t* pre = reinterpret_cast<uint32_t*>(smem + 8);               // [kHaloRows][ps]
     double* nrm = reinterpret_cast<double*>(smem + L.nrm);               // [kHaloRows][2 nw]
 
     const int64_t tt0 = t_begin + static_cast<int64_t>(blockIdx.x) * kSpsTile;
@@ -152,23 +171,59 @@ __global__ __launch_bounds__(256) void sps_detect_kernel(
     const int wave = tid >> 6, lane = tid & 63;
     const double* nj = norms + static_cast<int64_t>(j) * ndm * (2 * nw);
 
-    // halo row r (trial d0 - 1 + r) belongs to wave r % 4: its normalisation and its D
-    // columns, pre[r][1 + i] = D[t_tile0 - 1 + i], lanes over columns (coalesced)
+    // halo row r (trial d0 - 1 + r) belongs to wave r % 4: its normalisation, and the
+    // prefix sums of its D columns, pre[r][j] = sum of D[t_tile0 - 1 + i] for i < j
+    // (modulo 2^32: every window sum is exact below 2^32), for j < pw
     {
         const int64_t col0 = tt0 - 1 - dd_t0;          // plane column of i = 0
+        const int nq = (kSpsTile + sc.wmax + 3) / 4;   // 4-column groups from t_tile0 on
+        // a tile inside an aligned plane loads 16 bytes per lane and scans in registers
+        const bool fast = col0 >= 0 && col0 + 1 + 4 * nq <= dd_n && ((col0 + 1) & 3) == 0 && (dd_pitch & 3) == 0 &&
+                          (reinterpret_cast<uintptr_t>(dd) & 15) == 0;
         const int ilo = col0 < 0 ? static_cast<int>(-col0) : 0;
         const int ihi = static_cast<int>(min<int64_t>(tw, dd_n - col0));
         for (int r = wave; r < kHaloRows; r += 4) {
             const int d = d0 - 1 + r;
             const bool in = d >= 0 && d < ndm;
             if (lane < 2 * nw) nrm[r * 2 * nw + lane] = in ? nj[static_cast<int64_t>(d) * (2 * nw) + lane] : 0.0;
-            uint32_t* prow = pre + r * pw;
-            if (lane == 0) prow[0] = 0u;
-            if (in) {
-                const int32_t* src = dd + static_cast<int64_t>(d) * dd_pitch + col0;
-                for (int i = lane; i < tw; i += 64) prow[1 + i] = (i >= ilo && i < ihi) ? static_cast<uint32_t>(src[i]) : 0u;
+            uint32_t* prow = pre + r * ps;
+            if (!in) {
+                for (int i = lane; i < ps; i += 64) prow[i] = 0u;
+                continue;
+            }
+            const int32_t* src = dd + static_cast<int64_t>(d) * dd_pitch + col0;
+            if (fast) {
+                // lane holds columns t_tile0 + 4u .. + 3, u = lane, lane + 64, ...
+                const uint32_t first = static_cast<uint32_t>(src[0]);
+                uint32_t carry = first;
+                for (int u0 = 0; u0 < nq; u0 += 64) {
+                    const int u = u0 + lane;
+                    u32x4_t x = {0u, 0u, 0u, 0u};
+                    if (u < nq) x = *reinterpret_cast<const u32x4_t*>(src + 1 + 4 * u);
+                    const uint32_t a = x[0], b = a + x[1], c = b + x[2], e = c + x[3];
+                    const uint32_t incl = wave_incl_scan(e);
+                    const uint32_t base = carry + (incl - e);
+                    if (u < nq) *reinterpret_cast<u32x4_t*>(prow + 2 + 4 * u) = u32x4_t{base + a, base + b, base + c, base + e};
+                    carry += static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(incl), 63));
+                }
+                if (lane == 0) {
+                    prow[0] = 0u;
+                    prow[1] = first;
+                }
             } else {
-                for (int i = lane; i < tw; i += 64) prow[1 + i] = 0u;
+                // columns outside the plane count as 0; then the prefix in place, by the
+                // same wave (LDS operations of one wave complete in order)
+                if (lane == 0) prow[0] = 0u;
+                for (int i = lane; i < tw; i += 64) prow[1 + i] = (i >= ilo && i < ihi) ? static_cast<uint32_t>(src[i]) : 0u;
+                const int per = (pw + 63) / 64;
+                const int a = lane * per, b = min(a + per, pw);
+                uint32_t s = 0;
+                for (int i = a; i < b; ++i) s += prow[i];
+                uint32_t run = wave_incl_scan(s) - s;
+                for (int i = a; i < b; ++i) {
+                    run += prow[i];
+                    prow[i] = run;
+                }
             }
         }
     }
@@ -203,28 +258,6 @@ __global__ __launch_bounds__(256) void sps_detect_kernel(
         }
     }
     __syncthreads();
-    // inclusive prefix per row, one wave per row, modulo 2^32 (exact window sums < 2^32)
-    {
-        const int per = (pw + 63) / 64;
-        for (int r = wave; r < kHaloRows; r += 4) {
-            uint32_t* pr = pre + r * pw;
-            const int a = lane * per, b = min(a + per, pw);
-            uint32_t s = 0;
-            for (int i = a; i < b; ++i) s += pr[i];
-            uint32_t incl = s;
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const uint32_t u = __shfl_up(incl, o, 64);
-                if (lane >= o) incl += u;
-            }
-            uint32_t run = incl - s;
-            for (int i = a; i < b; ++i) {
-                run += pr[i];
-                pr[i] = run;
-            }
-        }
-    }
-    __syncthreads();
     if constexpr (EXACT) {
         double* best = reinterpret_cast<double*>(smem + L.tail);         // [kHaloRows][kHaloCols]
         __shared__ int32_t cnt[kSpsRows];
@@ -233,7 +266,7 @@ __global__ __launch_bounds__(256) void sps_detect_kernel(
             const int r = i / kHaloCols, c = i - r * kHaloCols;
             const int d = d0 - 1 + r;
             const int64_t t = tt0 - 1 + c;
-            best[i] = exact_best(pre, pw, nrm, sc, r, c, d >= 0 && d < ndm && t >= lo && t < hi);
+            best[i] = exact_best(pre, ps, nrm, sc, r, c, d >= 0 && d < ndm && t >= lo && t < hi);
         }
         __syncthreads();
         // 3x3 peak test for the inner rows, 64 consecutive starts per wave step
@@ -268,7 +301,7 @@ __global__ __launch_bounds__(256) void sps_detect_kernel(
             const int ri = wave + 4 * h, r = ri + 1;
             const int d = d0 + ri;
             if (d >= ndm) break;
-            const uint32_t* pr = pre + r * pw + 1 + lane;   // prefix at start tt0 + 64 q + lane
+            const uint32_t* pr = pre + r * ps + 1 + lane;   // prefix at start tt0 + 64 q + lane
             const int4* sk = scr + ri * nw;
             uint32_t neg0[4];
             float v[4];
@@ -301,7 +334,7 @@ __global__ __launch_bounds__(256) void sps_detect_kernel(
                     auto val = [&](int rr_, int cc) {
                         const int dr = d0 - 1 + rr_;
                         const int64_t tr = tt0 - 1 + cc;
-                        return exact_best(pre, pw, nrm, sc, rr_, cc, dr >= 0 && dr < ndm && tr >= lo && tr < hi);
+                        return exact_best(pre, ps, nrm, sc, rr_, cc, dr >= 0 && dr < ndm && tr >= lo && tr < hi);
                     };
                     const int c0 = 64 * q + lane + 1;
                     const double x = val(r, c0);
