@@ -37,12 +37,14 @@ struct DedispVariant {
     int lds_bytes;   // LDS budget per work-group (both buffers)
     int layout;      // 0/3: lane owns 16 contiguous samples (ds_read_b128; 4-way or 16-way switch)
                      // 1/2: four 4-sample groups (ds_read2_b32; 2 reuses equal-offset windows)
-                     // 4: matrix-core contraction (v_mfma_i32_32x32x32_i8), see below
+                     // 4: matrix-core contraction (v_mfma_i32_32x32x32_i8), 4 channels x 8
+                     //    residuals per step, see below
+                     // 5: the same contraction with 8 channels x 4 residuals per step
     int tile;        // output samples per work-group (time tile)
     int depth;       // staging buffers in the LDS ring (loads run depth - 1 steps ahead)
     int max_tiles;   // layout 4: a channel block spans at most 32 * max_tiles rows of t' (31 or 63)
 };
-constexpr int kNumDedispVariants = 17;
+constexpr int kNumDedispVariants = 18;
 
 // Matrix-core variant (layout 4). Within a block of up to 32 trials (first trial d0)
 // and a run of channels, the shift splits exactly as
@@ -50,28 +52,34 @@ constexpr int kNumDedispVariants = 17;
 // For rows t' of a shifted time axis, the partial sum over the run,
 //   P[t'][d] = sum_c X[c][t' + base[c] + r[d][c]],
 // is a product of the matrix A[t'][(c, r)] = X[c][t' + base[c] + r] with the one-hot
-// matrix B[(c, r)][d] = (r == r[d][c]). D[d][t] receives P[t + E[d]][d]. One
-// MFMA step contracts 4 channels x 8 residuals. A channel block ends where the
-// residual range of the next 4 channels would reach 8.
+// matrix B[(c, r)][d] = (r == r[d][c]). D[d][t] receives P[t + E[d]][d]. One MFMA step
+// contracts CPS channels x 32/CPS residuals: 4 x 8 (layout 4) or 8 x 4 (layout 5). A
+// channel block ends where the residual range of the next CPS channels would reach
+// 32/CPS.
 // A channel block spans at most 32 * max_tiles rows of t', with max_tiles 63 or 31. A
 // staged row then needs at most 32 * max_tiles + 26 bytes: 2048 or 1024 bytes of LDS.
-constexpr int kMfmaRec = 256;           // per-step table record (bytes)
+constexpr int mfma_cps(int layout) { return layout == 5 ? 8 : 4; }
 constexpr int mfma_row_bytes(int max_tiles) { return max_tiles <= 31 ? 1024 : 2048; }
-// LDS of a work-group: int32 accumulator tile [tile][32], then `depth` staging
-// buffers of 4 rows, then `depth` records.
-constexpr int mfma_lds_bytes(int tile, int depth, int max_tiles) {
-    return tile * 32 * 4 + depth * (4 * mfma_row_bytes(max_tiles) + kMfmaRec);
+// Record of one DM block and step k (D = the variant's depth), CPS channels per step:
+//   [0, 32 CPS)   u8  8*r[d][CPS k + i] at CPS d + i (d < 32, i < CPS)
+//   e             i16 e[d] = E[d] - min E of the channel block holding step k (32 of them)
+//   phase         u8  phase of the CPS staged rows (their start mod 16)
+//   tiles         i32 rows of t' in 32-row tiles for that channel block
+//   left          i32 steps of the channel block from step k on (k included)
+//   next_need     i32 16-byte chunks each row of step k + D - 1 needs
+//   max_e         i32 max e over the channel block's trials
+//   next_rs       i32 16-aligned row starts (relative to the time tile) of step k + D - 1
+struct MfmaRec {
+    int size, e, phase, tiles, left, next_need, max_e, next_rs;
+};
+constexpr MfmaRec mfma_rec(int cps) {
+    return cps == 8 ? MfmaRec{512, 256, 320, 328, 332, 336, 340, 352} : MfmaRec{256, 128, 192, 200, 204, 208, 212, 224};
 }
-// Record layout (one per DM block and 4-channel step k; D = the variant's depth):
-//   [0, 128)    u8  8*r[d][4k+i] at 4d+i (d < 32, i < 4)
-//   [128, 192)  i16 e[d] = E[d] - min E of the channel block holding step k
-//   [192, 196)  u8  phase of the 4 staged rows (their start mod 16)
-//   [196, 200)  i32 rows of t' in 32-row tiles for that channel block
-//   [200, 204)  i32 steps of the channel block from step k on (k included)
-//   [204, 208)  i32 16-byte chunks each row of step k + D - 1 needs
-//   [208, 224)  i32 16-aligned row starts (relative to the time tile) of step k + D - 1
-//   [224, 228)  i32 max e over the channel block's trials
-constexpr int kRecE = 128, kRecPhase = 192, kRecTiles = 196, kRecLeft = 200, kRecNextNeed = 204, kRecNextRs = 208, kRecMaxE = 224;
+// LDS of a work-group: int32 accumulator tile [tile][32], then `depth` staging
+// buffers of CPS rows, then `depth` records.
+constexpr int mfma_lds_bytes(int tile, int depth, int max_tiles, int cps = 4) {
+    return tile * 32 * 4 + depth * (cps * mfma_row_bytes(max_tiles) + mfma_rec(cps).size);
+}
 extern const DedispVariant kDedispVariants[kNumDedispVariants];
 constexpr int kDefaultDedispVariant = 12;   // i8 matrix cores, 16 waves
 
@@ -141,9 +149,10 @@ struct aa_plan_s {
 namespace aa {
 // Builds (host) and uploads (device, unless the plan is host-only) the tables of a variant.
 int prepare_variant(aa_plan_s* p, int variant);
-// Host tables of the matrix-core variant: DM blocks, 16-aligned staged-row starts
-// [nblk][nchan4] and the per-step records [nblk][nchan4 / 4][kMfmaRec].
-int build_mfma_tables(const aa_plan_s* p, int tile, int depth, int max_tiles, std::vector<DmBlock>& blocks,
+// Host tables of the matrix-core variants: DM blocks, 16-aligned staged-row starts
+// [nblk][nchan_pad] and the per-step records [nblk][nchan_pad / cps][record size], with
+// nchan_pad = nchan rounded up to cps channels.
+int build_mfma_tables(const aa_plan_s* p, int tile, int depth, int max_tiles, int cps, std::vector<DmBlock>& blocks,
                       std::vector<int32_t>& rsv, std::vector<uint8_t>& rec);
 void free_tables(DedispTables& t);
 // Launchers (dedisp.hip, sps.hip). Arguments are validated by the callers.

@@ -334,25 +334,26 @@ __device__ __forceinline__ void wait_vmcnt(int n) {
     }
 }
 
-// Matrix-core dedispersion of one (DM block, time tile), layout 4. The shift of a
-// trial d of the block at channel c is s = base[c] + E[d] + r[d][c], with 0 <= r < 8
-// inside a channel block (the tables are built on the host, tiling.cpp). So
+// Matrix-core dedispersion of one (DM block, time tile), layouts 4 and 5. The shift
+// of a trial d of the block at channel c is s = base[c] + E[d] + r[d][c], with
+// 0 <= r < R inside a channel block (the tables are built on the host, tiling.cpp). So
 //   D[d][t] = sum over channel blocks of P[t + e[d]][d],
 //   P[t'][d] = sum_{c in block} X[c][t' + base[c] + min E + r[d][c]],
 // where t' runs over a shifted time axis and e[d] = E[d] - min E. P is a product of
-// the data matrix A[t'][(c, r)] (a sliding 8-byte window per channel) and the one-hot
+// the data matrix A[t'][(c, r)] (a sliding R-byte window per channel) and the one-hot
 // matrix B[(c, r)][d], computed exactly by v_mfma_i32_32x32x32_i8: rows are 32 values
-// of t', columns the 32 trials, and one step contracts 4 channels x 8 residuals.
+// of t', columns the 32 trials, and one step contracts CPS channels x R residuals,
+// CPS x R = 32 (4 x 8 for layout 4, 8 x 4 for layout 5).
 // Input bytes enter as x - 128 (signed 8-bit), and 128 * nchan is added back at the end.
 //  * W = 8 or 16 waves. Wave w owns the tiles w + W j of 32 rows of t' (a channel block
 //    needs TILE / 32 to MAXT tiles, MAXT = 63 or 31, so a wave owns NT = TILE / (32 W)
-//    .. ceil(MAXT / W) of them) and holds their 32 x 32 int32 accumulators in registers. Each channel block runs a loop specialised
-//    for the wave's NT, so the hot loop has no per-tile branches; the loop is bound by
-//    instruction issue, not by the matrix cores.
+//    .. ceil(MAXT / W) of them) and holds their 32 x 32 int32 accumulators in
+//    registers. Each channel block runs a loop specialised for the wave's NT, so the hot
+//    loop has no per-tile branches.
 //  * At the end of a channel block, each accumulator row t' of trial d is added into
 //    the work-group's [TILE][32] int32 tile in LDS at t = t' - e[d] (ds_add_u32). Lanes
 //    hold 32 distinct trials of one row, so these adds are conflict-free.
-//  * Input rows are staged 4 channels per step, up to ROW = 2048 (MAXT 63) or 1024
+//  * Input rows are staged CPS channels per step, up to ROW = 2048 (MAXT 63) or 1024
 //    (MAXT 31) bytes each, by direct global->LDS loads into a ring of DEPTH buffers,
 //    issued DEPTH - 1 steps ahead. Each staging wave loads 1024 bytes of one row.
 //    Each step's table record (residuals, e, phases, tile and step counts, and the row
@@ -360,7 +361,8 @@ __device__ __forceinline__ void wait_vmcnt(int n) {
 //    Every staging wave issues exactly one data load per step, and wave 0 also the
 //    record, so waiting until only the newer steps' loads are in flight makes a step's
 //    data complete. Lanes past a row's needed length load a duplicate of its first chunk.
-//  * A lane (row m, half h) reads its two channels' windows as 3 aligned dwords each
+//  * A lane (row m, half h) holds channels CPS/2 h .. CPS/2 h + CPS/2 - 1 of the step.
+//    It reads each channel's R-byte window as aligned dwords (3 for R = 8, 2 for R = 4)
 //    and aligns them with v_alignbyte_b32. Every staged chunk that a needed byte lives
 //    in is in range; chunks wholly outside [0, n_in16) are clamped to a valid address,
 //    and their bytes only reach rows that are never written out.
@@ -368,52 +370,57 @@ struct MfmaCtx {
     const DedispArgs* A;
     const uint8_t* recg;   // this DM block's records
     int64_t t0, last16;
-    int K4, wave, lane, m, h, row, half, vlane, ps;
+    int K, wave, lane, m, h, row, half, vlane, ps;
     bool interior;         // every staged row of the tile lies inside [0, n_in16)
 };
 
-// Where the next step's loads go: `c` is the wave's channel, `rowp` its input row
-// at the time tile (A.in + c * in_pitch + t0) and `recp` the step's record.
-struct MfmaNext {
-    int c;
-    const uint8_t* rowp;
-    const uint8_t* recp;
-    __device__ __forceinline__ void advance(int64_t step_bytes) {
-        c += 4;
-        rowp += step_bytes;
-        recp += kMfmaRec;
-    }
-};
-
-template <int TILE, int DEPTH, int MAXT>
+template <int TILE, int DEPTH, int MAXT, int CPS>
 struct MfmaLayout {
     static constexpr int ROW = mfma_row_bytes(MAXT);  // staged bytes per channel row
     static constexpr int PARTS = ROW / 1024;          // staging waves per row
-    static constexpr int SW = 4 * PARTS;              // staging waves
-    static constexpr int STAGE = 4 * ROW;
+    static constexpr int SW = CPS * PARTS;            // staging waves
+    static constexpr int STAGE = CPS * ROW;
+    static constexpr MfmaRec RL = mfma_rec(CPS);      // record layout
     static constexpr int ACC = TILE * 32 * 4;
     static constexpr int RING = ACC;                  // byte offsets into LDS
     static constexpr int RECS = ACC + DEPTH * STAGE;
 };
 
+// Where the next step's loads go: `c` is the wave's channel, `rowp` its input row
+// at the time tile (A.in + c * in_pitch + t0) and `recp` the step's record.
+template <int CPS>
+struct MfmaNext {
+    int c;
+    const uint8_t* rowp;
+    const uint8_t* recp;
+    __device__ __forceinline__ void advance(int64_t step_bytes) {
+        c += CPS;
+        rowp += step_bytes;
+        recp += mfma_rec(CPS).size;
+    }
+};
+
 // Loads of step k into ring slot `slot`: each staging wave stages 1024 bytes of a
 // channel row (16 bytes per lane, `need` chunks of the row), then wave 0 the step's
 // record.
-template <int TILE, int DEPTH, int MAXT>
-__device__ __forceinline__ void mfma_issue(const MfmaCtx& cx, uint8_t* lds, const MfmaNext& nx, int slot, int rs,
+template <int TILE, int DEPTH, int MAXT, int CPS>
+__device__ __forceinline__ void mfma_issue(const MfmaCtx& cx, uint8_t* lds, const MfmaNext<CPS>& nx, int slot, int rs,
                                            int need) {
-    using L = MfmaLayout<TILE, DEPTH, MAXT>;
+    using L = MfmaLayout<TILE, DEPTH, MAXT, CPS>;
     const DedispArgs& A = *cx.A;
     if (cx.wave >= L::SW) return;                      // waves 0 .. SW - 1 stage the rows
     const int v = cx.vlane < need ? cx.vlane : 0;
     uint8_t* dst = lds + L::RING + slot * L::STAGE + cx.row * L::ROW + cx.half * 1024;
+    // plain pointer types keep the load builtins' arguments out of template dependence
+    const uint8_t* rowp = nx.rowp;
+    const uint8_t* recp = nx.recp;
     if (nx.c < A.nchan) {
         if (cx.interior) {
-            __builtin_amdgcn_global_load_lds(nx.rowp + rs + 16 * v, (lds_void*)dst, 16, 0, 0);
+            __builtin_amdgcn_global_load_lds(rowp + rs + 16 * v, (lds_void*)dst, 16, 0, 0);
         } else {
             const int64_t first = cx.t0 + rs;           // wave-uniform
             const int top = need < 64 * cx.half + 64 ? need : 64 * cx.half + 64;
-            const uint8_t* row0 = nx.rowp - cx.t0;      // the row at sample 0
+            const uint8_t* row0 = rowp - cx.t0;         // the row at sample 0
             if (first >= 0 && first + 16 * top <= A.n_in16) {
                 __builtin_amdgcn_global_load_lds(row0 + first + 16 * v, (lds_void*)dst, 16, 0, 0);
             } else {
@@ -425,74 +432,118 @@ __device__ __forceinline__ void mfma_issue(const MfmaCtx& cx, uint8_t* lds, cons
     } else {
         __builtin_amdgcn_global_load_lds(A.pad + 16 * v, (lds_void*)dst, 16, 0, 0);
     }
-    if (cx.wave == 0)
-        __builtin_amdgcn_global_load_lds(nx.recp + 4 * cx.lane, (lds_void*)(lds + L::RECS + slot * kMfmaRec), 4, 0, 0);
+    if (cx.wave == 0) {
+        uint8_t* rdst = lds + L::RECS + slot * L::RL.size;
+        if constexpr (L::RL.size == 256) {
+            __builtin_amdgcn_global_load_lds(recp + 4 * cx.lane, (lds_void*)rdst, 4, 0, 0);
+        } else {
+            static_assert(L::RL.size == 512, "record size");
+            if (cx.lane < 32) __builtin_amdgcn_global_load_lds(recp + 16 * cx.lane, (lds_void*)rdst, 16, 0, 0);
+        }
+    }
 }
 
 // Wait until step k's loads are complete: the steps k + 1 .. k + DEPTH - 2 may still
 // be in flight (constant count in the steady state), then barrier.
 template <int DEPTH>
 __device__ __forceinline__ void mfma_wait(const MfmaCtx& cx, int k) {
-    if (k + DEPTH - 2 < cx.K4) {
+    if (k + DEPTH - 2 < cx.K) {
         if (cx.ps == 2)
             vmcnt_le<2 * (DEPTH - 2)>();
         else if (cx.ps == 1)
             vmcnt_le<DEPTH - 2>();
     } else {
-        wait_vmcnt((cx.K4 - 1 - k) * cx.ps);
+        wait_vmcnt((cx.K - 1 - k) * cx.ps);
     }
     __builtin_amdgcn_s_barrier();
 }
 
 // The steps [k0, k1) of one channel block, with NT tiles for this wave (tiles
 // wave + W j). `slot` is the ring slot of step k0 on entry and of step k1 on exit.
-template <int NT, int W, int TILE, int DEPTH, int MAXT>
-__device__ __forceinline__ void mfma_block(const MfmaCtx& cx, uint8_t* lds, int k0, int k1, int& slot, MfmaNext& nx,
-                                           int64_t step_bytes, i32x16 (&acc)[(MAXT + W - 1) / W]) {
-    using L = MfmaLayout<TILE, DEPTH, MAXT>;
-    const int lane_base = L::RING + 2 * cx.h * L::ROW + 32 * cx.wave + cx.m;
+template <int NT, int W, int TILE, int DEPTH, int MAXT, int CPS>
+__device__ __forceinline__ void mfma_block(const MfmaCtx& cx, uint8_t* lds, int k0, int k1, int& slot,
+                                           MfmaNext<CPS>& nx, int64_t step_bytes,
+                                           i32x16 (&acc)[(MAXT + W - 1) / W]) {
+    using L = MfmaLayout<TILE, DEPTH, MAXT, CPS>;
+    constexpr int HC = CPS / 2;                        // channels per lane
+    const int lane_base = L::RING + HC * cx.h * L::ROW + 32 * cx.wave + cx.m;
 #pragma unroll 1
     for (int k = k0; k < k1; ++k) {
         if (k > k0) mfma_wait<DEPTH>(cx, k);
-        const int rec = L::RECS + slot * kMfmaRec;
+        const int rec = L::RECS + slot * L::RL.size;
         // every wave is done with the buffer of step k - 1: refill it with step k + DEPTH - 1
-        if (k + DEPTH - 1 < cx.K4) {
-            const int need = __builtin_amdgcn_readfirstlane(*reinterpret_cast<const int32_t*>(lds + rec + kRecNextNeed));
+        if (k + DEPTH - 1 < cx.K) {
+            const int need = __builtin_amdgcn_readfirstlane(*reinterpret_cast<const int32_t*>(lds + rec + L::RL.next_need));
             const int rs = __builtin_amdgcn_readfirstlane(
-                *reinterpret_cast<const int32_t*>(lds + rec + kRecNextRs + 4 * cx.row));
-            mfma_issue<TILE, DEPTH, MAXT>(cx, lds, nx, slot == 0 ? DEPTH - 1 : slot - 1, rs, need);
+                *reinterpret_cast<const int32_t*>(lds + rec + L::RL.next_rs + 4 * cx.row));
+            mfma_issue<TILE, DEPTH, MAXT, CPS>(cx, lds, nx, slot == 0 ? DEPTH - 1 : slot - 1, rs, need);
             nx.advance(step_bytes);
         }
-        // one-hot B: lane (trial m, half h) holds channels 2h, 2h+1 of the step
-        const uint32_t r32 = *reinterpret_cast<const uint32_t*>(lds + rec + 4 * cx.m);
-        const uint32_t ph = *reinterpret_cast<const uint16_t*>(lds + rec + kRecPhase + 2 * cx.h);
-        const uint32_t sh0 = (r32 >> (16 * cx.h)) & 0xFFu, sh1 = (r32 >> (16 * cx.h + 8)) & 0xFFu;
-        const uint64_t o0 = 1ull << sh0, o1 = 1ull << sh1;
-        const i32x4 B = {static_cast<int32_t>(o0), static_cast<int32_t>(o0 >> 32), static_cast<int32_t>(o1),
-                         static_cast<int32_t>(o1 >> 32)};
-        // data A: lane (row m, half h) reads 8-byte windows of channels 2h, 2h+1
         const int base = lane_base + slot * L::STAGE;
-        const int a0 = base + static_cast<int>(ph & 0xFFu), a1 = base + L::ROW + static_cast<int>(ph >> 8);
-        const int w0 = a0 & ~3, w1 = a1 & ~3;
-        const uint32_t u0 = static_cast<uint32_t>(a0 & 3), u1 = static_cast<uint32_t>(a1 & 3);
-        uint32_t x[NT][3], y[NT][3];
+        if constexpr (CPS == 4) {
+            // one-hot B: lane (trial m, half h) holds channels 2h, 2h+1 of the step
+            const uint32_t r32 = *reinterpret_cast<const uint32_t*>(lds + rec + 4 * cx.m);
+            const uint32_t ph = *reinterpret_cast<const uint16_t*>(lds + rec + L::RL.phase + 2 * cx.h);
+            const uint32_t sh0 = (r32 >> (16 * cx.h)) & 0xFFu, sh1 = (r32 >> (16 * cx.h + 8)) & 0xFFu;
+            const uint64_t o0 = 1ull << sh0, o1 = 1ull << sh1;
+            const i32x4 B = {static_cast<int32_t>(o0), static_cast<int32_t>(o0 >> 32), static_cast<int32_t>(o1),
+                             static_cast<int32_t>(o1 >> 32)};
+            // data A: lane (row m, half h) reads 8-byte windows of channels 2h, 2h+1
+            const int a0 = base + static_cast<int>(ph & 0xFFu), a1 = base + L::ROW + static_cast<int>(ph >> 8);
+            const int w0 = a0 & ~3, w1 = a1 & ~3;
+            const uint32_t u0 = static_cast<uint32_t>(a0 & 3), u1 = static_cast<uint32_t>(a1 & 3);
+            uint32_t x[NT][3], y[NT][3];
 #pragma unroll
-        for (int j = 0; j < NT; ++j) {
-            const uint32_t* p0 = reinterpret_cast<const uint32_t*>(lds + w0 + 32 * W * j);
-            const uint32_t* p1 = reinterpret_cast<const uint32_t*>(lds + w1 + 32 * W * j);
+            for (int j = 0; j < NT; ++j) {
+                const uint32_t* p0 = reinterpret_cast<const uint32_t*>(lds + w0 + 32 * W * j);
+                const uint32_t* p1 = reinterpret_cast<const uint32_t*>(lds + w1 + 32 * W * j);
 #pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                x[j][i] = p0[i];
-                y[j][i] = p1[i];
+                for (int i = 0; i < 3; ++i) {
+                    x[j][i] = p0[i];
+                    y[j][i] = p1[i];
+                }
             }
-        }
 #pragma unroll
-        for (int j = 0; j < NT; ++j) {
-            const i32x4 Av = {static_cast<int32_t>(__builtin_amdgcn_alignbyte(x[j][1], x[j][0], u0) ^ 0x80808080u),
-                              static_cast<int32_t>(__builtin_amdgcn_alignbyte(x[j][2], x[j][1], u0) ^ 0x80808080u),
-                              static_cast<int32_t>(__builtin_amdgcn_alignbyte(y[j][1], y[j][0], u1) ^ 0x80808080u),
-                              static_cast<int32_t>(__builtin_amdgcn_alignbyte(y[j][2], y[j][1], u1) ^ 0x80808080u)};
-            acc[j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(Av, B, acc[j], 0, 0, 0);
+            for (int j = 0; j < NT; ++j) {
+                const i32x4 Av = {static_cast<int32_t>(__builtin_amdgcn_alignbyte(x[j][1], x[j][0], u0) ^ 0x80808080u),
+                                  static_cast<int32_t>(__builtin_amdgcn_alignbyte(x[j][2], x[j][1], u0) ^ 0x80808080u),
+                                  static_cast<int32_t>(__builtin_amdgcn_alignbyte(y[j][1], y[j][0], u1) ^ 0x80808080u),
+                                  static_cast<int32_t>(__builtin_amdgcn_alignbyte(y[j][2], y[j][1], u1) ^ 0x80808080u)};
+                acc[j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(Av, B, acc[j], 0, 0, 0);
+            }
+        } else {
+            // one-hot B: lane (trial m, half h) holds channels 4h .. 4h+3 of the step, a
+            // byte 8 r per channel; the dword of channel i is 1 << 8 r
+            const uint32_t r32 = *reinterpret_cast<const uint32_t*>(lds + rec + 8 * cx.m + 4 * cx.h);
+            const uint32_t ph = *reinterpret_cast<const uint32_t*>(lds + rec + L::RL.phase + 4 * cx.h);
+            const i32x4 B = {static_cast<int32_t>(1u << (r32 & 31u)), static_cast<int32_t>(1u << ((r32 >> 8) & 31u)),
+                             static_cast<int32_t>(1u << ((r32 >> 16) & 31u)), static_cast<int32_t>(1u << ((r32 >> 24) & 31u))};
+            // data A: lane (row m, half h) reads 4-byte windows of channels 4h .. 4h+3
+            int w[4];
+            uint32_t u[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int ai = base + i * L::ROW + static_cast<int>((ph >> (8 * i)) & 0xFFu);
+                w[i] = ai & ~3;
+                u[i] = static_cast<uint32_t>(ai & 3);
+            }
+            uint32_t x[NT][4][2];
+#pragma unroll
+            for (int j = 0; j < NT; ++j)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const uint32_t* pi = reinterpret_cast<const uint32_t*>(lds + w[i] + 32 * W * j);
+                    x[j][i][0] = pi[0];
+                    x[j][i][1] = pi[1];
+                }
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                const i32x4 Av = {static_cast<int32_t>(__builtin_amdgcn_alignbyte(x[j][0][1], x[j][0][0], u[0]) ^ 0x80808080u),
+                                  static_cast<int32_t>(__builtin_amdgcn_alignbyte(x[j][1][1], x[j][1][0], u[1]) ^ 0x80808080u),
+                                  static_cast<int32_t>(__builtin_amdgcn_alignbyte(x[j][2][1], x[j][2][0], u[2]) ^ 0x80808080u),
+                                  static_cast<int32_t>(__builtin_amdgcn_alignbyte(x[j][3][1], x[j][3][0], u[3]) ^ 0x80808080u)};
+                acc[j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(Av, B, acc[j], 0, 0, 0);
+            }
         }
         slot = slot + 1 == DEPTH ? 0 : slot + 1;
     }
@@ -503,22 +554,23 @@ __device__ __forceinline__ void mfma_block(const MfmaCtx& cx, uint8_t* lds, int 
 template <int N, int U, int TPW>
 constexpr int clamp_nt() { return N < U ? U : (N > TPW ? TPW : N); }
 
-template <int W, int TILE, int DEPTH, int MAXT>
+template <int W, int TILE, int DEPTH, int MAXT, int CPS>
 __device__ __forceinline__ void dedisp_mfma_tile(const DedispArgs& A, int blk, int64_t t0) {
     // wave w owns the tiles w + W j (j < TPW); a channel block has at least TILE / 32
     // tiles, so each wave owns at least U of them
     constexpr int TPW = (MAXT + W - 1) / W, U = TILE / (32 * W);
-    using L = MfmaLayout<TILE, DEPTH, MAXT>;
+    using L = MfmaLayout<TILE, DEPTH, MAXT, CPS>;
     static_assert((W == 8 || W == 16) && TILE % 32 == 0 && U >= 1 && U <= TPW && TPW <= 8 && DEPTH >= 3 &&
-                  DEPTH <= 13 && (MAXT == 31 || MAXT == 63) && 32 * MAXT >= TILE, "waves / tile / depth / span");
+                  DEPTH <= 13 && (MAXT == 31 || MAXT == 63) && 32 * MAXT >= TILE && (CPS == 4 || CPS == 8) &&
+                  L::SW <= W, "waves / tile / depth / span / channels per step");
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     int32_t* acc_lds = reinterpret_cast<int32_t*>(lds);
     MfmaCtx cx;
     cx.A = &A;
     cx.t0 = t0;
     cx.last16 = A.n_in16 - 16;
-    cx.K4 = A.nchan_pad >> 2;
-    cx.recg = reinterpret_cast<const uint8_t*>(A.offs) + static_cast<int64_t>(blk) * cx.K4 * kMfmaRec;
+    cx.K = A.nchan_pad / CPS;
+    cx.recg = reinterpret_cast<const uint8_t*>(A.offs) + static_cast<int64_t>(blk) * cx.K * L::RL.size;
     const int tid = threadIdx.x;
     cx.wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     cx.lane = tid & 63;
@@ -534,17 +586,17 @@ __device__ __forceinline__ void dedisp_mfma_tile(const DedispArgs& A, int blk, i
         const DmBlock bk = A.blocks[blk];
         cx.interior = t0 + bk.rs_lo >= 0 && t0 + bk.rs_hi + L::ROW <= A.n_in16;
     }
-    const int64_t step_bytes = 4 * A.in_pitch;
-    MfmaNext nx{cx.row, A.in + static_cast<int64_t>(cx.row) * A.in_pitch + t0, cx.recg};
+    const int64_t step_bytes = CPS * A.in_pitch;
+    MfmaNext<CPS> nx{cx.row, A.in + static_cast<int64_t>(cx.row) * A.in_pitch + t0, cx.recg};
 
     for (int i = tid; i < L::ACC / 16; i += 64 * W) reinterpret_cast<u32x4*>(lds)[i] = u32x4{0u, 0u, 0u, 0u};
     int rs_pro[DEPTH - 1];
 #pragma unroll
     for (int j = 0; j < DEPTH - 1; ++j)
-        rs_pro[j] = j < cx.K4 ? __builtin_amdgcn_readfirstlane(rsv[4 * j + cx.row]) : 0;
+        rs_pro[j] = j < cx.K ? __builtin_amdgcn_readfirstlane(rsv[CPS * j + cx.row]) : 0;
 #pragma unroll
     for (int j = 0; j < DEPTH - 1; ++j) {
-        if (j < cx.K4) mfma_issue<TILE, DEPTH, MAXT>(cx, lds, nx, j, rs_pro[j], L::ROW / 16);
+        if (j < cx.K) mfma_issue<TILE, DEPTH, MAXT, CPS>(cx, lds, nx, j, rs_pro[j], L::ROW / 16);
         nx.advance(step_bytes);
     }
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
@@ -555,23 +607,25 @@ __device__ __forceinline__ void dedisp_mfma_tile(const DedispArgs& A, int blk, i
     const uint32_t acc_base =
         static_cast<uint32_t>(reinterpret_cast<uintptr_t>((__attribute__((address_space(3))) int32_t*)acc_lds));
     int slot = 0;
-    for (int k0 = 0; k0 < cx.K4;) {
+    for (int k0 = 0; k0 < cx.K;) {
         mfma_wait<DEPTH>(cx, k0);
-        const int rec0 = L::RECS + slot * kMfmaRec;
-        const int nr = __builtin_amdgcn_readfirstlane(*reinterpret_cast<const int32_t*>(lds + rec0 + kRecTiles));
-        const int k1 = k0 + __builtin_amdgcn_readfirstlane(*reinterpret_cast<const int32_t*>(lds + rec0 + kRecLeft));
+        const int rec0 = L::RECS + slot * L::RL.size;
+        const int nr = __builtin_amdgcn_readfirstlane(*reinterpret_cast<const int32_t*>(lds + rec0 + L::RL.tiles));
+        const int k1 = k0 + __builtin_amdgcn_readfirstlane(*reinterpret_cast<const int32_t*>(lds + rec0 + L::RL.left));
         const int nt = (nr - cx.wave + W - 1) / W;      // tiles of this wave, U .. TPW
         // one inlined loop per value in [U, TPW] (nt = 1 only reaches the default case)
         switch (nt) {
-#define AA_NT(N)                                                                                                  \
-    case N:                                                                                                       \
-        if constexpr (N >= U && N <= TPW)                                                                         \
-            mfma_block<clamp_nt<N, U, TPW>(), W, TILE, DEPTH, MAXT>(cx, lds, k0, k1, slot, nx, step_bytes, acc); \
+#define AA_NT(N)                                                                                           \
+    case N:                                                                                                \
+        if constexpr (N >= U && N <= TPW)                                                                  \
+            mfma_block<clamp_nt<N, U, TPW>(), W, TILE, DEPTH, MAXT, CPS>(cx, lds, k0, k1, slot, nx, step_bytes, \
+                                                                         acc);                              \
         break;
             AA_NT(8) AA_NT(7) AA_NT(6) AA_NT(5) AA_NT(4) AA_NT(3) AA_NT(2)
 #undef AA_NT
             default:
-                if constexpr (U == 1) mfma_block<1, W, TILE, DEPTH, MAXT>(cx, lds, k0, k1, slot, nx, step_bytes, acc);
+                if constexpr (U == 1)
+                    mfma_block<1, W, TILE, DEPTH, MAXT, CPS>(cx, lds, k0, k1, slot, nx, step_bytes, acc);
                 break;
         }
         // flush: accumulator register i of lane (m, h) holds row 8 (i / 4) + 4 h + i % 4
@@ -581,9 +635,9 @@ __device__ __forceinline__ void dedisp_mfma_tile(const DedispArgs& A, int blk, i
         // before the final read. A tile whose rows land in [0, TILE) for every e in
         // [0, max e] adds with immediate offsets and no checks.
         const int last = slot == 0 ? DEPTH - 1 : slot - 1;   // slot of step k1 - 1
-        const int lrec = L::RECS + last * kMfmaRec;
-        const int e = *reinterpret_cast<const int16_t*>(lds + lrec + kRecE + 2 * cx.m);
-        const int emax = __builtin_amdgcn_readfirstlane(*reinterpret_cast<const int32_t*>(lds + lrec + kRecMaxE));
+        const int lrec = L::RECS + last * L::RL.size;
+        const int e = *reinterpret_cast<const int16_t*>(lds + lrec + L::RL.e + 2 * cx.m);
+        const int emax = __builtin_amdgcn_readfirstlane(*reinterpret_cast<const int32_t*>(lds + lrec + L::RL.max_e));
 #pragma unroll
         for (int j = 0; j < TPW; ++j) {
             const int q = cx.wave + W * j;
@@ -641,8 +695,8 @@ __device__ __forceinline__ void dedisp_mfma_tile(const DedispArgs& A, int blk, i
 template <int DPW, int W, int LAYOUT, int TILE = kTimeTile, int DEPTH = 2, int MAXT = 63, int WPE = 1>
 __global__ __launch_bounds__(64 * W, WPE) void dedisp_kernel(DedispArgs a) {
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
-    if constexpr (LAYOUT == 4)
-        dedisp_mfma_tile<W, TILE, DEPTH, MAXT>(a, bid % a.nblk, static_cast<int64_t>(bid / a.nblk) * TILE);
+    if constexpr (LAYOUT == 4 || LAYOUT == 5)
+        dedisp_mfma_tile<W, TILE, DEPTH, MAXT, mfma_cps(LAYOUT)>(a, bid % a.nblk, static_cast<int64_t>(bid / a.nblk) * TILE);
     else
         dedisp_tile<DPW, W, LAYOUT>(a, bid % a.nblk, static_cast<int64_t>(bid / a.nblk) * kTimeTile);
 }
@@ -675,8 +729,9 @@ __global__ __launch_bounds__(64 * W, WPE) void dedisp_batch_kernel(const DedispA
         }
         const DedispArgs a = args[lo];
         const int64_t local = it - item_begin[lo];
-        if constexpr (LAYOUT == 4)
-            dedisp_mfma_tile<W, TILE, DEPTH, MAXT>(a, static_cast<int>(local % a.nblk), (local / a.nblk) * TILE);
+        if constexpr (LAYOUT == 4 || LAYOUT == 5)
+            dedisp_mfma_tile<W, TILE, DEPTH, MAXT, mfma_cps(LAYOUT)>(a, static_cast<int>(local % a.nblk),
+                                                                     (local / a.nblk) * TILE);
         else
             dedisp_tile<DPW, W, LAYOUT>(a, static_cast<int>(local % a.nblk), (local / a.nblk) * kTimeTile);
         __syncthreads();   // the next item restages LDS buffer 0
@@ -693,7 +748,7 @@ typedef void (*DedispBatchFn)(const DedispArgs*, const int64_t*, int, int64_t, u
 #define AA_VARIANTS(K)                                                                           \
     K<4, 4, 1>, K<2, 8, 1>, K<4, 8, 1>, K<2, 16, 1>, K<2, 8, 0>, K<4, 4, 0>, K<2, 8, 3>, K<4, 4, 3>, \
         K<2, 8, 2>, K<4, 8, 2>, K<4, 4, 2>, K<4, 8, 4, 1024, 3>, K<2, 16, 4, 1024, 3>, K<2, 16, 4, 768, 7>, \
-        K<4, 8, 4, 512, 3, 31, 4>, K<2, 16, 4, 512, 3, 31, 8>, K<4, 8, 4, 480, 4, 31, 4>
+        K<4, 8, 4, 512, 3, 31, 4>, K<2, 16, 4, 512, 3, 31, 8>, K<4, 8, 4, 480, 4, 31, 4>, K<2, 16, 5, 864, 3, 63>
 const DedispFn kKernels[kNumDedispVariants] = {AA_VARIANTS(dedisp_kernel)};
 const DedispBatchFn kBatchKernels[kNumDedispVariants] = {AA_VARIANTS(dedisp_batch_kernel)};
 #undef AA_VARIANTS
@@ -735,7 +790,7 @@ int launch_dedisperse(const aa_plan_s* p, int variant, const uint8_t* d_in, int6
     const DedispArgs a = dedisp_args(p, variant, d_in, in_pitch, n_in, d_out, out_pitch);
     const int64_t grid = a.ntile * a.nblk;
     if (grid > 0x7fffffff) return fail(AA_EINVAL, "aa_dedisperse: too many tiles for one launch");
-    const size_t lds = V.layout == 4 ? static_cast<size_t>(V.lds_bytes) : static_cast<size_t>(2 * kChanPerPass) * T.max_row;
+    const size_t lds = V.layout >= 4 ? static_cast<size_t>(V.lds_bytes) : static_cast<size_t>(2 * kChanPerPass) * T.max_row;
     hipLaunchKernelGGL(kKernels[variant], dim3(static_cast<unsigned>(grid)), dim3(64 * V.waves), lds, stream, a);
     AA_HIP(hipGetLastError());
     return AA_OK;
@@ -744,7 +799,7 @@ int launch_dedisperse(const aa_plan_s* p, int variant, const uint8_t* d_in, int6
 int launch_dedisperse_batch(int variant, const DedispArgs* d_args, const int64_t* d_item_begin, int nbeams,
                             int64_t total, unsigned long long* d_counter, int max_row, hipStream_t stream) {
     const DedispVariant& V = kDedispVariants[variant];
-    const size_t lds = V.layout == 4 ? static_cast<size_t>(V.lds_bytes) : static_cast<size_t>(2 * kChanPerPass) * max_row;
+    const size_t lds = V.layout >= 4 ? static_cast<size_t>(V.lds_bytes) : static_cast<size_t>(2 * kChanPerPass) * max_row;
     int dev = 0, cus = 0, per_cu = 0;
     AA_HIP(hipGetDevice(&dev));
     AA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));

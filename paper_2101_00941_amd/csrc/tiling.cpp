@@ -31,6 +31,8 @@ const DedispVariant kDedispVariants[kNumDedispVariants] = {
     {14, 8, 4, mfma_lds_bytes(512, 3, 31), 4, 512, 3, 31},     // 512 threads, 4 tiles per wave
     {15, 16, 2, mfma_lds_bytes(512, 3, 31), 4, 512, 3, 31},    // 1024 threads, 2 tiles per wave
     {16, 8, 4, mfma_lds_bytes(480, 4, 31), 4, 480, 4, 31},     // 512 threads, 4 tiles per wave
+    // 8 channels x 4 residuals per step
+    {17, 16, 2, mfma_lds_bytes(864, 3, 63, 8), 5, 864, 3, 63},  // 1024 threads, 4 tiles per wave
 };
 
 void free_tables(DedispTables& t) {
@@ -50,24 +52,28 @@ int upload(T** dst, const std::vector<T>& src) {
 }
 }  // namespace
 
-// Tables of the matrix-core variant (layout 4). f(d, c) = s[d][c] - s[d0][c].
-//  * DM blocks: up to 32 consecutive trials such that every 4-channel step on its own
-//    has a residual range below 8 (so a channel block always holds at least one step)
-//    and, for every channel, the spread of f over the block's trials is at most
+// Tables of the matrix-core variants (layouts 4 and 5). f(d, c) = s[d][c] - s[d0][c];
+// a step is `cps` consecutive channels and R = 32 / cps is the residual range.
+//  * DM blocks: up to 32 consecutive trials such that every step on its own has a
+//    residual range below R (so a channel block always holds at least one step) and,
+//    for every channel, the spread of f over the block's trials is at most
 //    (max_tiles * 32 - tile). The spread of E over a channel block is bounded
 //    by that, so a channel block never needs more than max_tiles tiles of t'.
 //    A single trial always qualifies (f = 0).
-//  * Channel blocks: greedy runs of 4-channel steps whose residual range stays below 8.
+//  * Channel blocks: greedy runs of steps whose residual range stays below R.
 //    E[d] = min over the run of f(d, c), r = f - E, e = E - min E, and the staged row
 //    of channel c starts at s[d0][c] + min E (16-aligned start + phase).
 //  * Padded channels (c >= nchan) are staged from a row of 0x80 bytes, which the kernel
 //    maps to 0, so their residuals are 0. Absent trials of a short block have r = 0,
 //    e = 0 and are not written out.
-int build_mfma_tables(const aa_plan_s* p, int tile, int depth, int max_tiles, std::vector<DmBlock>& blocks,
+int build_mfma_tables(const aa_plan_s* p, int tile, int depth, int max_tiles, int cps, std::vector<DmBlock>& blocks,
                       std::vector<int32_t>& rsv, std::vector<uint8_t>& rec) {
     const int nchan = p->nchan;
-    const int nchan4 = (nchan + 3) & ~3;
-    const int K4 = nchan4 / 4;
+    if (cps != 4 && cps != 8) return fail(AA_EINVAL, "matrix-core tiling: 4 or 8 channels per step");
+    const int R = 32 / cps;
+    const int npad = (nchan + cps - 1) / cps * cps;
+    const int K = npad / cps;
+    const MfmaRec RL = mfma_rec(cps);
     const int spread_max = max_tiles * 32 - tile;
     const int row = mfma_row_bytes(max_tiles);
     if (tile % 32 || tile < 256 || spread_max < 0 || depth < 3 || (max_tiles != 31 && max_tiles != 63))
@@ -82,15 +88,15 @@ int build_mfma_tables(const aa_plan_s* p, int tile, int depth, int max_tiles, st
         while (count < 32 && d0 + count < p->ndm) {
             const int d = d0 + count;
             bool ok = true;
-            for (int c0 = 0; c0 < nchan && ok; c0 += 4) {
+            for (int c0 = 0; c0 < nchan && ok; c0 += cps) {
                 int lo = INT32_MAX, hi = INT32_MIN;
-                for (int c = c0; c < std::min(c0 + 4, nchan); ++c) {
+                for (int c = c0; c < std::min(c0 + cps, nchan); ++c) {
                     const int32_t f = S(d, c) - S(d0, c);
                     lo = std::min(lo, f);
                     hi = std::max(hi, f);
                     if (std::max(fmax[c], f) - std::min(fmin[c], f) > spread_max) ok = false;
                 }
-                if (hi - lo > 7) ok = false;
+                if (hi - lo > R - 1) ok = false;
             }
             if (!ok) break;
             for (int c = 0; c < nchan; ++c) {
@@ -104,38 +110,38 @@ int build_mfma_tables(const aa_plan_s* p, int tile, int depth, int max_tiles, st
         d0 += count;
     }
     const size_t nblk = blocks.size();
-    rsv.assign(nblk * nchan4, 0);
-    rec.assign(nblk * K4 * kMfmaRec, 0);
+    rsv.assign(nblk * npad, 0);
+    rec.assign(nblk * K * RL.size, 0);
     std::vector<int32_t> lo(32), hi(32);
     for (size_t bi = 0; bi < nblk; ++bi) {
         const int d0 = blocks[bi].first, count = blocks[bi].count;
-        uint8_t* R = &rec[bi * K4 * kMfmaRec];
-        for (int k0 = 0; k0 < K4;) {
+        uint8_t* Rb = &rec[bi * K * RL.size];
+        for (int k0 = 0; k0 < K;) {
             // grow the channel block [k0, k1) step by step
             std::fill(lo.begin(), lo.end(), INT32_MAX);
             std::fill(hi.begin(), hi.end(), INT32_MIN);
             int k1 = k0;
-            while (k1 < K4) {
+            while (k1 < K) {
                 bool ok = true;
                 for (int i = 0; i < count && ok; ++i) {
                     int l = lo[i], h = hi[i];
-                    for (int c = 4 * k1; c < std::min(4 * k1 + 4, nchan); ++c) {
+                    for (int c = cps * k1; c < std::min(cps * k1 + cps, nchan); ++c) {
                         const int32_t f = S(d0 + i, c) - S(d0, c);
                         l = std::min(l, f);
                         h = std::max(h, f);
                     }
-                    if (h - l > 7) ok = false;
+                    if (h - l > R - 1) ok = false;
                 }
                 if (!ok) break;
                 for (int i = 0; i < count; ++i)
-                    for (int c = 4 * k1; c < std::min(4 * k1 + 4, nchan); ++c) {
+                    for (int c = cps * k1; c < std::min(cps * k1 + cps, nchan); ++c) {
                         const int32_t f = S(d0 + i, c) - S(d0, c);
                         lo[i] = std::min(lo[i], f);
                         hi[i] = std::max(hi[i], f);
                     }
                 ++k1;
             }
-            if (k1 == k0) return fail(AA_EINVAL, "matrix-core tiling: a 4-channel step exceeds the residual range");
+            if (k1 == k0) return fail(AA_EINVAL, "matrix-core tiling: a step exceeds the residual range");
             int32_t emin = INT32_MAX, emax = INT32_MIN;
             for (int i = 0; i < count; ++i) {
                 emin = std::min(emin, lo[i]);
@@ -144,40 +150,40 @@ int build_mfma_tables(const aa_plan_s* p, int tile, int depth, int max_tiles, st
             const int tiles = (emax - emin + tile + 31) / 32;
             if (tiles > max_tiles) return fail(AA_EINVAL, "matrix-core tiling: channel block spread too large");
             for (int k = k0; k < k1; ++k) {
-                uint8_t* rk = R + static_cast<size_t>(k) * kMfmaRec;
-                for (int j = 0; j < 4; ++j) {
-                    const int c = 4 * k + j;
+                uint8_t* rk = Rb + static_cast<size_t>(k) * RL.size;
+                for (int j = 0; j < cps; ++j) {
+                    const int c = cps * k + j;
                     const int32_t v = c < nchan ? S(d0, c) + emin : 0;
-                    rsv[bi * nchan4 + c] = v & ~15;
-                    rk[kRecPhase + j] = static_cast<uint8_t>(v & 15);
+                    rsv[bi * npad + c] = v & ~15;
+                    rk[RL.phase + j] = static_cast<uint8_t>(v & 15);
                     for (int i = 0; i < count && c < nchan; ++i) {
                         const int32_t r = S(d0 + i, c) - S(d0, c) - lo[i];
-                        rk[4 * i + j] = static_cast<uint8_t>(8 * r);
+                        rk[cps * i + j] = static_cast<uint8_t>(8 * r);
                     }
                 }
                 for (int i = 0; i < count; ++i) {
                     const int16_t e = static_cast<int16_t>(lo[i] - emin);
-                    std::memcpy(rk + kRecE + 2 * i, &e, 2);
+                    std::memcpy(rk + RL.e + 2 * i, &e, 2);
                 }
                 const int32_t left = k1 - k, emax_rel = emax - emin;
-                std::memcpy(rk + kRecTiles, &tiles, 4);
-                std::memcpy(rk + kRecLeft, &left, 4);
-                std::memcpy(rk + kRecMaxE, &emax_rel, 4);
+                std::memcpy(rk + RL.tiles, &tiles, 4);
+                std::memcpy(rk + RL.left, &left, 4);
+                std::memcpy(rk + RL.max_e, &emax_rel, 4);
             }
             k0 = k1;
         }
-        blocks[bi].rs_lo = *std::min_element(rsv.begin() + bi * nchan4, rsv.begin() + (bi + 1) * nchan4);
-        blocks[bi].rs_hi = *std::max_element(rsv.begin() + bi * nchan4, rsv.begin() + (bi + 1) * nchan4);
+        blocks[bi].rs_lo = *std::min_element(rsv.begin() + bi * npad, rsv.begin() + (bi + 1) * npad);
+        blocks[bi].rs_hi = *std::max_element(rsv.begin() + bi * npad, rsv.begin() + (bi + 1) * npad);
         // row starts and lengths of step k + depth - 1, read by the kernel when it issues
         // that step's loads. A row needs the bytes [0, 32 tiles + phase + 11).
-        for (int k = 0; k + depth - 1 < K4; ++k) {
-            uint8_t* rk = R + static_cast<size_t>(k) * kMfmaRec;
-            const uint8_t* rn = R + static_cast<size_t>(k + depth - 1) * kMfmaRec;
-            std::memcpy(rk + kRecNextRs, &rsv[bi * nchan4 + 4 * (k + depth - 1)], 16);
+        for (int k = 0; k + depth - 1 < K; ++k) {
+            uint8_t* rk = Rb + static_cast<size_t>(k) * RL.size;
+            const uint8_t* rn = Rb + static_cast<size_t>(k + depth - 1) * RL.size;
+            std::memcpy(rk + RL.next_rs, &rsv[bi * npad + cps * (k + depth - 1)], 4 * cps);
             int32_t tiles;
-            std::memcpy(&tiles, rn + kRecTiles, 4);
+            std::memcpy(&tiles, rn + RL.tiles, 4);
             const int32_t need = std::min(row / 16, (32 * tiles + 15 + 11 + 15) / 16);
-            std::memcpy(rk + kRecNextNeed, &need, 4);
+            std::memcpy(rk + RL.next_need, &need, 4);
         }
     }
     return AA_OK;
@@ -188,10 +194,11 @@ int prepare_mfma(const aa_plan_s* p, const DedispVariant& V, DedispTables& t) {
     std::vector<DmBlock> blocks;
     std::vector<int32_t> rsv;
     std::vector<uint8_t> rec;
-    const int rc0 = build_mfma_tables(p, V.tile, V.depth, V.max_tiles, blocks, rsv, rec);
+    const int cps = mfma_cps(V.layout);
+    const int rc0 = build_mfma_tables(p, V.tile, V.depth, V.max_tiles, cps, blocks, rsv, rec);
     if (rc0 != AA_OK) return rc0;
     t.bd = 32;
-    t.nchan_pad = (p->nchan + 3) & ~3;
+    t.nchan_pad = (p->nchan + cps - 1) / cps * cps;
     t.max_row = mfma_row_bytes(V.max_tiles);
     t.blocks = blocks;
     if (p->device >= 0) {
@@ -211,7 +218,7 @@ int prepare_variant(aa_plan_s* p, int v) {
     DedispTables& T = p->tables[v];
     if (T.variant == v) return AA_OK;
     const DedispVariant& V = kDedispVariants[v];
-    if (V.layout == 4) {
+    if (V.layout == 4 || V.layout == 5) {
         DedispTables t;
         t.variant = v;
         const int rc = prepare_mfma(p, V, t);

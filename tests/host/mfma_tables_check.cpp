@@ -2,7 +2,7 @@
 // kernel's steps (staging with the same row starts, lengths and clamps, one-hot
 // residual selection, per-block flush at t' - e) over the tables that build_mfma_tables
 // produces, compared with D[d][t] = sum_c X[c][t + s[d][c]] computed directly.
-// Host-only plan: no GPU needed. Usage: mfma_tables_check TILE DEPTH [MAX_TILES]
+// Host-only plan: no GPU needed. Usage: mfma_tables_check TILE DEPTH [MAX_TILES [CPS]]
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -12,7 +12,7 @@
 
 using namespace aa;
 
-static int TILE = 1024, DEPTH = 3, MAXT = 63;
+static int TILE = 1024, DEPTH = 3, MAXT = 63, CPS = 4;
 static int run_case(int nchan, int nsamp, double ftop, double foff, double tsamp, std::vector<double> dms, unsigned seed,
                     int max_tiles_check = 1 << 30) {
     aa_plan_desc_t d{};
@@ -24,8 +24,10 @@ static int run_case(int nchan, int nsamp, double ftop, double foff, double tsamp
     if (aa_plan(&d, &p) != AA_OK) { printf("plan failed: %s\n", aa_last_error()); return 1; }
     std::vector<DmBlock> blocks; std::vector<int32_t> rsv; std::vector<uint8_t> rec;
     const int ROW = mfma_row_bytes(MAXT);
-    if (build_mfma_tables(p, TILE, DEPTH, MAXT, blocks, rsv, rec) != AA_OK) { printf("tables failed: %s\n", aa_last_error()); return 1; }
-    const int nchan4 = (nchan + 3) & ~3, K4 = nchan4 / 4;
+    const MfmaRec RL = mfma_rec(CPS);
+    const int RES = 32 / CPS;                      // residual range
+    if (build_mfma_tables(p, TILE, DEPTH, MAXT, CPS, blocks, rsv, rec) != AA_OK) { printf("tables failed: %s\n", aa_last_error()); return 1; }
+    const int nchan4 = (nchan + CPS - 1) / CPS * CPS, K4 = nchan4 / CPS;
     const int64_t M = p->maxshift, n_out = nsamp - M;
     const int64_t pitch = (nsamp + 255) / 256 * 256;
     const int64_t n_in16 = (nsamp + 15) & ~15;
@@ -38,24 +40,24 @@ static int run_case(int nchan, int nsamp, double ftop, double foff, double tsamp
     int maxnr = 0; double sumcb = 0; int ncb = 0;
     int tiles_done = 0;
     for (size_t bi = 0; bi < blocks.size(); ++bi) {
-        const uint8_t* R = &rec[bi * K4 * kMfmaRec];
-        for (int k = 0; k < K4; ++k) if (*(int32_t*)(R + k * kMfmaRec + kRecLeft) == 1) ncb++;
+        const uint8_t* R = &rec[bi * K4 * RL.size];
+        for (int k = 0; k < K4; ++k) if (*(int32_t*)(R + k * RL.size + RL.left) == 1) ncb++;
         for (int64_t ti = 0; ti < ntile && tiles_done < max_tiles_check; ++ti, ++tiles_done) {
             const int64_t t0 = ti * TILE;
             std::vector<int64_t> acc(TILE * 32, 0);
             std::vector<int64_t> C(64 * 32 * 32, 0);
             std::vector<int32_t> rs_hist(K4 * 4);
             for (int k = 0; k < K4; ++k) {
-                const uint8_t* rk = R + (size_t)k * kMfmaRec;
+                const uint8_t* rk = R + (size_t)k * RL.size;
                 // row starts as the kernel obtains them
-                int rs[4];
+                int rs[8];
                 int need = ROW / 16;
-                for (int i = 0; i < 4; ++i)
-                    rs[i] = k < DEPTH - 1 ? rsv[bi * nchan4 + 4 * k + i] : *(const int32_t*)(R + (size_t)(k - DEPTH + 1) * kMfmaRec + kRecNextRs + 4 * i);
-                if (k >= DEPTH - 1) need = *(const int32_t*)(R + (size_t)(k - DEPTH + 1) * kMfmaRec + kRecNextNeed);
-                uint8_t row[4][2048];
-                for (int i = 0; i < 4; ++i) {
-                    const int c = 4 * k + i;
+                for (int i = 0; i < CPS; ++i)
+                    rs[i] = k < DEPTH - 1 ? rsv[bi * nchan4 + CPS * k + i] : *(const int32_t*)(R + (size_t)(k - DEPTH + 1) * RL.size + RL.next_rs + 4 * i);
+                if (k >= DEPTH - 1) need = *(const int32_t*)(R + (size_t)(k - DEPTH + 1) * RL.size + RL.next_need);
+                static uint8_t row[8][2048];
+                for (int i = 0; i < CPS; ++i) {
+                    const int c = CPS * k + i;
                     for (int v0 = 0; v0 < ROW / 16; ++v0) {
                         const int v = v0 < need ? v0 : 0;
                         int64_t pos = t0 + rs[i] + 16 * v;
@@ -63,15 +65,15 @@ static int run_case(int nchan, int nsamp, double ftop, double foff, double tsamp
                         for (int b = 0; b < 16; ++b) row[i][16 * v0 + b] = c < nchan ? x[c * pitch + pos + b] : 0x80;
                     }
                 }
-                const int nr = *(const int32_t*)(rk + kRecTiles);
-                const int left = *(const int32_t*)(rk + kRecLeft);
+                const int nr = *(const int32_t*)(rk + RL.tiles);
+                const int left = *(const int32_t*)(rk + RL.left);
                 const int endf = left == 1;
                 // a channel block is a run of steps with one tile count and a step count
                 // that counts down to 1
                 if (k > 0) {
-                    const uint8_t* rp = rk - kMfmaRec;
-                    const int pleft = *(const int32_t*)(rp + kRecLeft);
-                    if (pleft > 1 && (pleft != left + 1 || *(const int32_t*)(rp + kRecTiles) != *(const int32_t*)(rk + kRecTiles))) {
+                    const uint8_t* rp = rk - RL.size;
+                    const int pleft = *(const int32_t*)(rp + RL.left);
+                    if (pleft > 1 && (pleft != left + 1 || *(const int32_t*)(rp + RL.tiles) != *(const int32_t*)(rk + RL.tiles))) {
                         printf("inconsistent block record at step %d\n", k);
                         return 1;
                     }
@@ -80,11 +82,11 @@ static int run_case(int nchan, int nsamp, double ftop, double foff, double tsamp
                 {
                     int emax = 0;
                     for (int dd = 0; dd < blocks[bi].count; ++dd) {
-                        const int e = *(const int16_t*)(rk + kRecE + 2 * dd);
+                        const int e = *(const int16_t*)(rk + RL.e + 2 * dd);
                         if (e < 0) { printf("negative e\n"); return 1; }
                         emax = e > emax ? e : emax;
                     }
-                    if (emax != *(const int32_t*)(rk + kRecMaxE)) { printf("max e mismatch at step %d\n", k); return 1; }
+                    if (emax != *(const int32_t*)(rk + RL.max_e)) { printf("max e mismatch at step %d\n", k); return 1; }
                 }
                 if (nr > maxnr) maxnr = nr;
                 if (nr > MAXT || nr < TILE / 32) { printf("bad nr %d\n", nr); return 1; }
@@ -92,22 +94,23 @@ static int run_case(int nchan, int nsamp, double ftop, double foff, double tsamp
                     for (int mrow = 0; mrow < 32; ++mrow)
                         for (int dd = 0; dd < 32; ++dd) {
                             int64_t s = 0;
-                            for (int h = 0; h < 2; ++h)
-                                for (int i = 0; i < 2; ++i) {
-                                    const int ch = 2 * h + i;
-                                    const int r = rk[4 * dd + ch] / 8;
-                                    const int ph = rk[kRecPhase + ch];
-                                    const int P = 32 * q + mrow + ph + r;
-                                    if (P >= ROW) { printf("window past row\n"); return 1; }
-                                    s += (int)(int8_t)(row[ch][P] ^ 0x80);   // (x ^ 0x80) as int8 = x - 128
-                                }
+                            for (int ch = 0; ch < CPS; ++ch) {
+                                const int r = rk[CPS * dd + ch] / 8;
+                                if (r >= RES) { printf("residual out of range\n"); return 1; }
+                                const int ph = rk[RL.phase + ch];
+                                // the kernel reads the aligned dwords covering the R-byte window
+                                const int a = 32 * q + mrow + ph;
+                                if ((a & ~3) + (RES == 8 ? 12 : 8) > ROW) { printf("window past row\n"); return 1; }
+                                const int P = a + r;
+                                s += (int)(int8_t)(row[ch][P] ^ 0x80);   // (x ^ 0x80) as int8 = x - 128
+                            }
                             C[(q * 32 + mrow) * 32 + dd] += s;
                         }
                 if (endf) {
                     for (int q = 0; q < nr; ++q)
                         for (int mrow = 0; mrow < 32; ++mrow)
                             for (int dd = 0; dd < 32; ++dd) {
-                                const int e = *(const int16_t*)(rk + kRecE + 2 * dd);
+                                const int e = *(const int16_t*)(rk + RL.e + 2 * dd);
                                 const int t = 32 * q + mrow - e;
                                 if (t >= 0 && t < TILE) acc[t * 32 + dd] += C[(q * 32 + mrow) * 32 + dd];
                             }
@@ -133,7 +136,8 @@ static int run_case(int nchan, int nsamp, double ftop, double foff, double tsamp
 int main(int argc, char** argv) {
     if (argc > 2) { TILE = atoi(argv[1]); DEPTH = atoi(argv[2]); }
     if (argc > 3) MAXT = atoi(argv[3]);
-    printf("tile %d depth %d max tiles %d\n", TILE, DEPTH, MAXT);
+    if (argc > 4) CPS = atoi(argv[4]);
+    printf("tile %d depth %d max tiles %d channels per step %d\n", TILE, DEPTH, MAXT, CPS);
     int rc = 0;
     rc |= run_case(1, 3000, 1400.0, 1.0, 64e-6, {0.0, 10.0, 100.0}, 1);
     rc |= run_case(7, 5003, 1500.0, 3.0, 64e-6, {0, 12.5, 25, 37.5, 50}, 2);
