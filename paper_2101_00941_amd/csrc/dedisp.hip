@@ -20,6 +20,7 @@
 //    every 256 channels.
 //  * No MFMA: this is shift-and-add, not a dense contraction.
 #include "aa_internal.h"
+#include "xcd.h"
 
 namespace aa {
 namespace {
@@ -30,11 +31,6 @@ typedef __attribute__((address_space(3))) void lds_void;
 // Work-group i runs on XCD i % 8. Give each XCD a contiguous run of logical tiles
 // (adjacent DM blocks of the same time tile), so that their overlapping input rows
 // are shared in that XCD's L2.
-__device__ __forceinline__ int xcd_remap(int bid, int n) {
-    const int q = n >> 3, r = n & 7;
-    const int x = bid & 7, k = bid >> 3;
-    return x * q + min(x, r) + k;
-}
 
 template <int Q>
 __device__ __forceinline__ void extract16(const u32x4& x0, const u32x4& x1, uint32_t sel0, uint32_t sel1,

@@ -19,6 +19,7 @@
 
 #include "aa_internal.h"
 #include "numerics.h"
+#include "xcd.h"
 
 namespace aa {
 namespace {
@@ -66,8 +67,25 @@ __global__ __launch_bounds__(256) void sps_stats_kernel(const int32_t* __restric
     const int64_t hi = min(lo + B, t_end);
     const int32_t* row = dd + static_cast<int64_t>(d) * dd_pitch - dd_t0;
     uint64_t s1 = 0, s2 = 0;
-    for (int64_t t = lo + threadIdx.x; t < hi; t += 256) {
-        const uint32_t v = static_cast<uint32_t>(row[t]);
+    // elements up to the first 16-byte boundary, then 4 per lane, then the tail
+    const uint32_t* p = reinterpret_cast<const uint32_t*>(row + lo);
+    const int64_t n = hi - lo;
+    const int64_t head = min<int64_t>(static_cast<int64_t>(((16u - (reinterpret_cast<uintptr_t>(p) & 15u)) & 15u) >> 2), n);
+    const int64_t n4 = (n - head) >> 2;
+    if (threadIdx.x < head) {
+        const uint32_t v = p[threadIdx.x];
+        s1 += v;
+        s2 += static_cast<uint64_t>(v) * v;
+    }
+    const u32x4_t* q = reinterpret_cast<const u32x4_t*>(p + head);
+    for (int64_t i = threadIdx.x; i < n4; i += 256) {
+        const u32x4_t v = q[i];
+        s1 += static_cast<uint64_t>(v[0]) + v[1] + v[2] + v[3];
+        s2 += static_cast<uint64_t>(v[0]) * v[0] + static_cast<uint64_t>(v[1]) * v[1] +
+              static_cast<uint64_t>(v[2]) * v[2] + static_cast<uint64_t>(v[3]) * v[3];
+    }
+    for (int64_t t = head + 4 * n4 + threadIdx.x; t < n; t += 256) {
+        const uint32_t v = p[t];
         s1 += v;
         s2 += static_cast<uint64_t>(v) * v;
     }
@@ -161,10 +179,15 @@ __global__ __launch_bounds__(256) void sps_detect_kernel(
     uint32_t* pre = reinterpret_cast<uint32_t*>(smem + 8);               // [kHaloRows][ps]
     double* nrm = reinterpret_cast<double*>(smem + L.nrm);               // [kHaloRows][2 nw]
 
-    const int64_t tt0 = t_begin + static_cast<int64_t>(blockIdx.x) * kSpsTile;
+    // XCD-aware order: each XCD walks consecutive time tiles of a row block, which share
+    // their halo columns in its L2
+    const int item = xcd_remap(static_cast<int>(blockIdx.x + blockIdx.y * gridDim.x),
+                               static_cast<int>(gridDim.x * gridDim.y));
+    const int bx = item % static_cast<int>(gridDim.x), by = item / static_cast<int>(gridDim.x);
+    const int64_t tt0 = t_begin + static_cast<int64_t>(bx) * kSpsTile;
     const int64_t tile_end = min(tt0 + kSpsTile, t_end);
-    const int d0 = blockIdx.y * kSpsRows;
-    const int j = static_cast<int>((static_cast<uint64_t>(blockIdx.x) * kSpsTile) / static_cast<uint32_t>(B));
+    const int d0 = by * kSpsRows;
+    const int j = static_cast<int>((static_cast<uint64_t>(bx) * kSpsTile) / static_cast<uint32_t>(B));
     const int64_t lo = max(tt0 - 1, static_cast<int64_t>(0));
     const int64_t hi = (t_total < 0 || tile_end < t_total) ? tile_end + 1 : tile_end;  // best valid in [lo, hi)
     const int tid = threadIdx.x;
@@ -478,6 +501,8 @@ int launch_single_pulse(const aa_plan_s* p, const int32_t* d_dd, int64_t dd_pitc
                        0, stream, d_dd, dd_pitch, dd_t0, t_begin, t_end, p->stat_block, p->ndm, sc, norms, rowcount);
     AA_HIP(hipGetLastError());
     const unsigned rowblocks = static_cast<unsigned>((p->ndm + kSpsRows - 1) / kSpsRows);
+    if (L.ntiles * static_cast<int64_t>(rowblocks) > 0x7fffffff)
+        return fail(AA_EINVAL, "aa_single_pulse: too many detection tiles for one launch");
     // the float32 screen needs every window sum below 2^31 (int32 centred sums)
     const bool screen = !d_best && static_cast<uint64_t>(p->nchan) * 255u * static_cast<uint64_t>(p->wmax) < (1ull << 31);
     const size_t lds = static_cast<size_t>(detect_lds(p->wmax, p->nwidths, !screen).total);
