@@ -454,18 +454,24 @@ __device__ __forceinline__ void mfma_wait(const MfmaCtx& cx, int k) {
     __builtin_amdgcn_s_barrier();
 }
 
+template <bool B>
+struct BoolTag {
+    static constexpr bool value = B;
+};
+
 // The steps [k0, k1) of one channel block, with NT tiles for this wave (tiles
 // wave + W j). `slot` is the ring slot of step k0 on entry and of step k1 on exit.
 template <int NT, int W, int TILE, int DEPTH, int MAXT, int CPS>
 __device__ __forceinline__ void mfma_block(const MfmaCtx& cx, uint8_t* lds, int k0, int k1, int& slot,
-                                           MfmaNext<CPS>& nx, int64_t step_bytes,
-                                           i32x16 (&acc)[(MAXT + W - 1) / W]) {
+                                           MfmaNext<CPS>& nx, int64_t step_bytes, uint32_t acc_base) {
     using L = MfmaLayout<TILE, DEPTH, MAXT, CPS>;
+    i32x16 acc[NT];
     constexpr int HC = CPS / 2;                        // channels per lane
     const int lane_base = L::RING + HC * cx.h * L::ROW + 32 * cx.wave + cx.m;
-#pragma unroll 1
-    for (int k = k0; k < k1; ++k) {
-        if (k > k0) mfma_wait<DEPTH>(cx, k);
+    // one step; the first step of a channel block starts its accumulators from zero
+    // (the matrix op's zero operand), so a flush needs no register clears
+    auto step = [&](int k, auto first) {
+        constexpr bool FIRST = decltype(first)::value;
         const int rec = L::RECS + slot * L::RL.size;
         // every wave is done with the buffer of step k - 1: refill it with step k + DEPTH - 1
         if (k + DEPTH - 1 < cx.K) {
@@ -505,7 +511,7 @@ __device__ __forceinline__ void mfma_block(const MfmaCtx& cx, uint8_t* lds, int 
                                   static_cast<int32_t>(__builtin_amdgcn_alignbyte(x[j][2], x[j][1], u0) ^ 0x80808080u),
                                   static_cast<int32_t>(__builtin_amdgcn_alignbyte(y[j][1], y[j][0], u1) ^ 0x80808080u),
                                   static_cast<int32_t>(__builtin_amdgcn_alignbyte(y[j][2], y[j][1], u1) ^ 0x80808080u)};
-                acc[j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(Av, B, acc[j], 0, 0, 0);
+                acc[j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(Av, B, FIRST ? i32x16{} : acc[j], 0, 0, 0);
             }
         } else {
             // one-hot B: lane (trial m, half h) holds channels 4h .. 4h+3 of the step, a
@@ -538,10 +544,47 @@ __device__ __forceinline__ void mfma_block(const MfmaCtx& cx, uint8_t* lds, int 
                                   static_cast<int32_t>(__builtin_amdgcn_alignbyte(x[j][1][1], x[j][1][0], u[1]) ^ 0x80808080u),
                                   static_cast<int32_t>(__builtin_amdgcn_alignbyte(x[j][2][1], x[j][2][0], u[2]) ^ 0x80808080u),
                                   static_cast<int32_t>(__builtin_amdgcn_alignbyte(x[j][3][1], x[j][3][0], u[3]) ^ 0x80808080u)};
-                acc[j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(Av, B, acc[j], 0, 0, 0);
+                acc[j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(Av, B, FIRST ? i32x16{} : acc[j], 0, 0, 0);
             }
         }
         slot = slot + 1 == DEPTH ? 0 : slot + 1;
+    };
+    step(k0, BoolTag<true>{});
+#pragma unroll 1
+    for (int k = k0 + 1; k < k1; ++k) {
+        mfma_wait<DEPTH>(cx, k);
+        step(k, BoolTag<false>{});
+    }
+    // flush: accumulator register i of lane (m, h) holds row 8 (i / 4) + 4 h + i % 4
+    // of the tile and trial m, which goes to t = row - e[m]. The adds are issued as
+    // inline ds_add_u32 so that the compiler does not wait for the staging loads in
+    // flight (they write other LDS bytes); the barrier after the tile's last block
+    // orders them before the final read. A tile whose rows land in [0, TILE) for every
+    // e in [0, max e] adds with immediate offsets and no checks.
+    const int last = slot == 0 ? DEPTH - 1 : slot - 1;   // slot of step k1 - 1
+    const int lrec = L::RECS + last * L::RL.size;
+    const int e = *reinterpret_cast<const int16_t*>(lds + lrec + L::RL.e + 2 * cx.m);
+    const int emax = __builtin_amdgcn_readfirstlane(*reinterpret_cast<const int32_t*>(lds + lrec + L::RL.max_e));
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        const int q = cx.wave + W * j;
+        if (32 * q >= emax && 32 * q + 32 <= TILE) {
+            const uint32_t tb = acc_base + 4u * static_cast<uint32_t>(cx.m + 32 * (32 * q + 4 * cx.h - e));
+#define AA_FLUSH(I) \
+    asm volatile("ds_add_u32 %0, %1 offset:%2" ::"v"(tb), "v"(acc[j][I]), "n"(128 * (8 * ((I) >> 2) + ((I) & 3))) : "memory");
+            AA_FLUSH(0) AA_FLUSH(1) AA_FLUSH(2) AA_FLUSH(3) AA_FLUSH(4) AA_FLUSH(5) AA_FLUSH(6) AA_FLUSH(7)
+            AA_FLUSH(8) AA_FLUSH(9) AA_FLUSH(10) AA_FLUSH(11) AA_FLUSH(12) AA_FLUSH(13) AA_FLUSH(14) AA_FLUSH(15)
+#undef AA_FLUSH
+        } else {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int t = 32 * q + 8 * (i >> 2) + 4 * cx.h + (i & 3) - e;
+                if (static_cast<unsigned>(t) < static_cast<unsigned>(TILE)) {
+                    const uint32_t addr = acc_base + 4u * static_cast<uint32_t>(32 * t + cx.m);
+                    asm volatile("ds_add_u32 %0, %1" ::"v"(addr), "v"(acc[j][i]) : "memory");
+                }
+            }
+        }
     }
 }
 
@@ -597,9 +640,6 @@ __device__ __forceinline__ void dedisp_mfma_tile(const DedispArgs& A, int blk, i
     }
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
 
-    i32x16 acc[TPW];
-#pragma unroll
-    for (int j = 0; j < TPW; ++j) acc[j] = i32x16{};
     const uint32_t acc_base =
         static_cast<uint32_t>(reinterpret_cast<uintptr_t>((__attribute__((address_space(3))) int32_t*)acc_lds));
     int slot = 0;
@@ -615,48 +655,14 @@ __device__ __forceinline__ void dedisp_mfma_tile(const DedispArgs& A, int blk, i
     case N:                                                                                                \
         if constexpr (N >= U && N <= TPW)                                                                  \
             mfma_block<clamp_nt<N, U, TPW>(), W, TILE, DEPTH, MAXT, CPS>(cx, lds, k0, k1, slot, nx, step_bytes, \
-                                                                         acc);                              \
+                                                                         acc_base);                         \
         break;
             AA_NT(8) AA_NT(7) AA_NT(6) AA_NT(5) AA_NT(4) AA_NT(3) AA_NT(2)
 #undef AA_NT
             default:
                 if constexpr (U == 1)
-                    mfma_block<1, W, TILE, DEPTH, MAXT, CPS>(cx, lds, k0, k1, slot, nx, step_bytes, acc);
+                    mfma_block<1, W, TILE, DEPTH, MAXT, CPS>(cx, lds, k0, k1, slot, nx, step_bytes, acc_base);
                 break;
-        }
-        // flush: accumulator register i of lane (m, h) holds row 8 (i / 4) + 4 h + i % 4
-        // of the tile and trial m, which goes to t = row - e[m]. The adds are issued as
-        // inline ds_add_u32 so that the compiler does not wait for the staging loads in
-        // flight (they write other LDS bytes); the barrier after the loop orders them
-        // before the final read. A tile whose rows land in [0, TILE) for every e in
-        // [0, max e] adds with immediate offsets and no checks.
-        const int last = slot == 0 ? DEPTH - 1 : slot - 1;   // slot of step k1 - 1
-        const int lrec = L::RECS + last * L::RL.size;
-        const int e = *reinterpret_cast<const int16_t*>(lds + lrec + L::RL.e + 2 * cx.m);
-        const int emax = __builtin_amdgcn_readfirstlane(*reinterpret_cast<const int32_t*>(lds + lrec + L::RL.max_e));
-#pragma unroll
-        for (int j = 0; j < TPW; ++j) {
-            const int q = cx.wave + W * j;
-            if (j < U || q < nr) {
-                if (32 * q >= emax && 32 * q + 32 <= TILE) {
-                    const uint32_t tb = acc_base + 4u * static_cast<uint32_t>(cx.m + 32 * (32 * q + 4 * cx.h - e));
-#define AA_FLUSH(I) \
-    asm volatile("ds_add_u32 %0, %1 offset:%2" ::"v"(tb), "v"(acc[j][I]), "n"(128 * (8 * ((I) >> 2) + ((I) & 3))) : "memory");
-                    AA_FLUSH(0) AA_FLUSH(1) AA_FLUSH(2) AA_FLUSH(3) AA_FLUSH(4) AA_FLUSH(5) AA_FLUSH(6) AA_FLUSH(7)
-                    AA_FLUSH(8) AA_FLUSH(9) AA_FLUSH(10) AA_FLUSH(11) AA_FLUSH(12) AA_FLUSH(13) AA_FLUSH(14) AA_FLUSH(15)
-#undef AA_FLUSH
-                } else {
-#pragma unroll
-                    for (int i = 0; i < 16; ++i) {
-                        const int t = 32 * q + 8 * (i >> 2) + 4 * cx.h + (i & 3) - e;
-                        if (static_cast<unsigned>(t) < static_cast<unsigned>(TILE)) {
-                            const uint32_t addr = acc_base + 4u * static_cast<uint32_t>(32 * t + cx.m);
-                            asm volatile("ds_add_u32 %0, %1" ::"v"(addr), "v"(acc[j][i]) : "memory");
-                        }
-                    }
-                }
-            }
-            acc[j] = i32x16{};
         }
         k0 = k1;
     }
