@@ -44,7 +44,7 @@ struct DedispVariant {
     int depth;       // staging buffers in the LDS ring (loads run depth - 1 steps ahead)
     int max_tiles;   // layout 4: a channel block spans at most 32 * max_tiles rows of t' (31 or 63)
 };
-constexpr int kNumDedispVariants = 18;
+constexpr int kNumDedispVariants = 20;
 
 // Matrix-core variant (layout 4). Within a block of up to 32 trials (first trial d0)
 // and a run of channels, the shift splits exactly as
@@ -75,10 +75,11 @@ struct MfmaRec {
 constexpr MfmaRec mfma_rec(int cps) {
     return cps == 8 ? MfmaRec{512, 256, 320, 328, 332, 336, 340, 352} : MfmaRec{256, 128, 192, 200, 204, 208, 212, 224};
 }
-// LDS of a work-group: int32 accumulator tile [tile][32], then `depth` staging
-// buffers of CPS rows, then `depth` records.
+// LDS of a work-group: int32 accumulator tile [tile + 2][32] (rows -1 and tile take the
+// adds that fall outside the tile and are never read), then `depth` staging buffers of
+// CPS rows, then `depth` records.
 constexpr int mfma_lds_bytes(int tile, int depth, int max_tiles, int cps = 4) {
-    return tile * 32 * 4 + depth * (cps * mfma_row_bytes(max_tiles) + mfma_rec(cps).size);
+    return (tile + 2) * 32 * 4 + depth * (cps * mfma_row_bytes(max_tiles) + mfma_rec(cps).size);
 }
 extern const DedispVariant kDedispVariants[kNumDedispVariants];
 constexpr int kDefaultDedispVariant = 12;   // i8 matrix cores, 16 waves

@@ -377,7 +377,8 @@ struct MfmaLayout {
     static constexpr int SW = CPS * PARTS;            // staging waves
     static constexpr int STAGE = CPS * ROW;
     static constexpr MfmaRec RL = mfma_rec(CPS);      // record layout
-    static constexpr int ACC = TILE * 32 * 4;
+    static constexpr int ACC = (TILE + 2) * 32 * 4;   // accumulator rows -1 .. TILE
+    static constexpr int ACC0 = 32 * 4;               // byte offset of row 0
     static constexpr int RING = ACC;                  // byte offsets into LDS
     static constexpr int RECS = ACC + DEPTH * STAGE;
 };
@@ -576,13 +577,14 @@ __device__ __forceinline__ void mfma_block(const MfmaCtx& cx, uint8_t* lds, int 
             AA_FLUSH(8) AA_FLUSH(9) AA_FLUSH(10) AA_FLUSH(11) AA_FLUSH(12) AA_FLUSH(13) AA_FLUSH(14) AA_FLUSH(15)
 #undef AA_FLUSH
         } else {
+            // rows outside [0, TILE) are clamped to the discarded rows -1 and TILE
+            const int tq = 32 * q + 4 * cx.h - e;
+            const uint32_t mb = acc_base + 4u * static_cast<uint32_t>(cx.m);
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
-                const int t = 32 * q + 8 * (i >> 2) + 4 * cx.h + (i & 3) - e;
-                if (static_cast<unsigned>(t) < static_cast<unsigned>(TILE)) {
-                    const uint32_t addr = acc_base + 4u * static_cast<uint32_t>(32 * t + cx.m);
-                    asm volatile("ds_add_u32 %0, %1" ::"v"(addr), "v"(acc[j][i]) : "memory");
-                }
+                const int t = min(max(tq + 8 * (i >> 2) + (i & 3), -1), TILE);
+                const uint32_t addr = mb + (static_cast<uint32_t>(t) << 7);   // 32 x 4 bytes per row
+                asm volatile("ds_add_u32 %0, %1" ::"v"(addr), "v"(acc[j][i]) : "memory");
             }
         }
     }
@@ -603,7 +605,7 @@ __device__ __forceinline__ void dedisp_mfma_tile(const DedispArgs& A, int blk, i
                   DEPTH <= 13 && (MAXT == 31 || MAXT == 63) && 32 * MAXT >= TILE && (CPS == 4 || CPS == 8) &&
                   L::SW <= W, "waves / tile / depth / span / channels per step");
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
-    int32_t* acc_lds = reinterpret_cast<int32_t*>(lds);
+    int32_t* acc_lds = reinterpret_cast<int32_t*>(lds + L::ACC0);   // row 0 of the accumulator tile
     MfmaCtx cx;
     cx.A = &A;
     cx.t0 = t0;
@@ -750,7 +752,8 @@ typedef void (*DedispBatchFn)(const DedispArgs*, const int64_t*, int, int64_t, u
 #define AA_VARIANTS(K)                                                                           \
     K<4, 4, 1>, K<2, 8, 1>, K<4, 8, 1>, K<2, 16, 1>, K<2, 8, 0>, K<4, 4, 0>, K<2, 8, 3>, K<4, 4, 3>, \
         K<2, 8, 2>, K<4, 8, 2>, K<4, 4, 2>, K<4, 8, 4, 1024, 3>, K<2, 16, 4, 1024, 3>, K<2, 16, 4, 768, 7>, \
-        K<4, 8, 4, 512, 3, 31, 4>, K<2, 16, 4, 512, 3, 31, 8>, K<4, 8, 4, 480, 4, 31, 4>, K<2, 16, 5, 864, 3, 63>
+        K<4, 8, 4, 512, 3, 31, 4>, K<2, 16, 4, 512, 3, 31, 8>, K<4, 8, 4, 480, 4, 31, 4>, K<2, 16, 5, 864, 3, 63>, \
+        K<2, 16, 4, 960, 4, 63>, K<2, 16, 4, 896, 5, 63>
 const DedispFn kKernels[kNumDedispVariants] = {AA_VARIANTS(dedisp_kernel)};
 const DedispBatchFn kBatchKernels[kNumDedispVariants] = {AA_VARIANTS(dedisp_batch_kernel)};
 #undef AA_VARIANTS

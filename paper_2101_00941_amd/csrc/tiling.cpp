@@ -33,6 +33,9 @@ const DedispVariant kDedispVariants[kNumDedispVariants] = {
     {16, 8, 4, mfma_lds_bytes(480, 4, 31), 4, 480, 4, 31},     // 512 threads, 4 tiles per wave
     // 8 channels x 4 residuals per step
     {17, 16, 2, mfma_lds_bytes(864, 3, 63, 8), 5, 864, 3, 63},  // 1024 threads, 4 tiles per wave
+    // deeper staging rings (loads 3 or 4 steps ahead) for slightly smaller tiles
+    {18, 16, 2, mfma_lds_bytes(960, 4, 63), 4, 960, 4, 63},     // 1024 threads, 4 tiles per wave
+    {19, 16, 2, mfma_lds_bytes(896, 5, 63), 4, 896, 5, 63},     // 1024 threads, 4 tiles per wave
 };
 
 void free_tables(DedispTables& t) {
