@@ -464,7 +464,8 @@ struct BoolTag {
 // wave + W j). `slot` is the ring slot of step k0 on entry and of step k1 on exit.
 template <int NT, int W, int TILE, int DEPTH, int MAXT, int CPS>
 __device__ __forceinline__ void mfma_block(const MfmaCtx& cx, uint8_t* lds, int k0, int k1, int& slot,
-                                           MfmaNext<CPS>& nx, int64_t step_bytes, uint32_t acc_base) {
+                                           MfmaNext<CPS>& nx, int64_t step_bytes, uint32_t acc_base, int e,
+                                           int emax) {
     using L = MfmaLayout<TILE, DEPTH, MAXT, CPS>;
     i32x16 acc[NT];
     constexpr int HC = CPS / 2;                        // channels per lane
@@ -561,11 +562,8 @@ __device__ __forceinline__ void mfma_block(const MfmaCtx& cx, uint8_t* lds, int 
     // inline ds_add_u32 so that the compiler does not wait for the staging loads in
     // flight (they write other LDS bytes); the barrier after the tile's last block
     // orders them before the final read. A tile whose rows land in [0, TILE) for every
-    // e in [0, max e] adds with immediate offsets and no checks.
-    const int last = slot == 0 ? DEPTH - 1 : slot - 1;   // slot of step k1 - 1
-    const int lrec = L::RECS + last * L::RL.size;
-    const int e = *reinterpret_cast<const int16_t*>(lds + lrec + L::RL.e + 2 * cx.m);
-    const int emax = __builtin_amdgcn_readfirstlane(*reinterpret_cast<const int32_t*>(lds + lrec + L::RL.max_e));
+    // e in [0, max e] adds with immediate offsets and no checks. (e[m] and max e are the
+    // same in every record of the block; the caller reads them from its first step.)
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
         const int q = cx.wave + W * j;
@@ -650,6 +648,8 @@ __device__ __forceinline__ void dedisp_mfma_tile(const DedispArgs& A, int blk, i
         const int rec0 = L::RECS + slot * L::RL.size;
         const int nr = __builtin_amdgcn_readfirstlane(*reinterpret_cast<const int32_t*>(lds + rec0 + L::RL.tiles));
         const int k1 = k0 + __builtin_amdgcn_readfirstlane(*reinterpret_cast<const int32_t*>(lds + rec0 + L::RL.left));
+        const int e = *reinterpret_cast<const int16_t*>(lds + rec0 + L::RL.e + 2 * cx.m);
+        const int emax = __builtin_amdgcn_readfirstlane(*reinterpret_cast<const int32_t*>(lds + rec0 + L::RL.max_e));
         const int nt = (nr - cx.wave + W - 1) / W;      // tiles of this wave, U .. TPW
         // one inlined loop per value in [U, TPW] (nt = 1 only reaches the default case)
         switch (nt) {
@@ -657,13 +657,14 @@ __device__ __forceinline__ void dedisp_mfma_tile(const DedispArgs& A, int blk, i
     case N:                                                                                                \
         if constexpr (N >= U && N <= TPW)                                                                  \
             mfma_block<clamp_nt<N, U, TPW>(), W, TILE, DEPTH, MAXT, CPS>(cx, lds, k0, k1, slot, nx, step_bytes, \
-                                                                         acc_base);                         \
+                                                                         acc_base, e, emax);                \
         break;
             AA_NT(8) AA_NT(7) AA_NT(6) AA_NT(5) AA_NT(4) AA_NT(3) AA_NT(2)
 #undef AA_NT
             default:
                 if constexpr (U == 1)
-                    mfma_block<1, W, TILE, DEPTH, MAXT, CPS>(cx, lds, k0, k1, slot, nx, step_bytes, acc_base);
+                    mfma_block<1, W, TILE, DEPTH, MAXT, CPS>(cx, lds, k0, k1, slot, nx, step_bytes, acc_base, e,
+                                                             emax);
                 break;
         }
         k0 = k1;
