@@ -2,11 +2,13 @@
 // section 2.2). Three kernels run in order on the caller's stream:
 //   sps_stats   exact int64 moments per (DM row, stat block), then mu and sigma in
 //               float64, then the per-width normalisation wmu_w = w*mu and
-//               r_w = 1/(sigma*sqrt(w)).
+//               r_w = 1/(sigma*sqrt(w)), and each width's smallest window sum whose
+//               S/N reaches the threshold.
 //   sps_detect  per (8 DM rows, 256 starts) tile: LDS prefix sums give the boxcars,
-//               best S/N is taken over widths in float64, and a 3x3 peak test runs on
-//               a one-sample, one-row halo. The result is a bit mask of candidates
-//               per row, plus integer per-row counts.
+//               an integer screen against those sums drops the cells whose best S/N
+//               is below the threshold, and the rest get the float64 best S/N and a
+//               3x3 peak test on a one-sample, one-row halo. The result is a bit mask
+//               of candidates per row, plus integer per-row counts.
 //   sps_emit    one work-group per DM row. The row's output offset is the sum of
 //               the counts of the rows before it. A block scan of the mask ranks each
 //               candidate, and the candidate is written in (dm, t) order. Its S/N and
@@ -55,11 +57,30 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
     return v;
 }
 
+// Screen threshold of one (row, width): the smallest window sum S in [0, 2^31) whose
+// S/N, computed as in exact_best, reaches the threshold. The S/N is non-decreasing in S
+// for r >= 0 (each float64 operation is monotone), so a cell's best S/N reaches the
+// threshold exactly when some width's sum reaches its threshold. The search starts at
+// the real crossing point and steps to the exact boundary; if it does not settle within
+// a few steps the threshold errs low (0), which only lets more cells through.
+constexpr uint32_t kNever = 0x80000000u;   // above every window sum on this path
+__device__ __forceinline__ uint32_t min_passing_sum(double wmu, double r, double threshold) {
+    auto reaches = [&](int64_t S) { return (static_cast<double>(S) - wmu) * r >= threshold; };
+    if (!(r > 0.0)) return (0.0 >= threshold) ? 0u : kNever;   // r = 0: every S/N is 0
+    const double x = wmu + threshold / r;
+    int64_t s = x <= 0.0 ? 0 : (x >= 2147483648.0 ? static_cast<int64_t>(kNever) : static_cast<int64_t>(__builtin_ceil(x)));
+    for (int i = 0; i < 16 && s > 0 && reaches(s - 1); ++i) --s;
+    if (s > 0 && reaches(s - 1)) return 0u;
+    for (int i = 0; i < 16 && s < static_cast<int64_t>(kNever) && !reaches(s); ++i) ++s;
+    return static_cast<uint32_t>(s);
+}
+
 // ---- statistics -------------------------------------------------------------
 __global__ __launch_bounds__(256) void sps_stats_kernel(const int32_t* __restrict__ dd, int64_t dd_pitch,
                                                         int64_t dd_t0, int64_t t_begin, int64_t t_end,
                                                         int32_t B, int32_t ndm, SpsConst sc,
-                                                        double* __restrict__ norms,
+                                                        double threshold, double* __restrict__ norms,
+                                                        uint32_t* __restrict__ smin,
                                                         int32_t* __restrict__ rowcount) {
     const int j = blockIdx.x;
     const int d = blockIdx.y;
@@ -108,9 +129,11 @@ __global__ __launch_bounds__(256) void sps_stats_kernel(const int32_t* __restric
         const double var = u128_to_double_rn(num) / static_cast<double>(n * n);
         const double sigma = __builtin_sqrt(var);
         double* out = norms + (static_cast<int64_t>(j) * ndm + d) * (2 * sc.nw);
+        uint32_t* so = smin + (static_cast<int64_t>(j) * ndm + d) * sc.nw;
         for (int k = 0; k < sc.nw; ++k) {
             out[k] = static_cast<double>(sc.widths[k]) * mu;
             out[sc.nw + k] = sigma == 0.0 ? 0.0 : 1.0 / (sigma * sc.sqrtw[k]);
+            so[k] = min_passing_sum(out[k], out[sc.nw + k], threshold);
         }
         if (j == 0) rowcount[d] = 0;
     }
@@ -122,9 +145,8 @@ constexpr int kHaloCols = kSpsTile + 2;
 
 // LDS of a detection work-group, in this order: 8 bytes, prefix sums [kHaloRows][ps]
 // (u32, row stride ps >= kSpsTile + 2 + wmax, a multiple of 4, so that entry 2 of every
-// row is 16-byte aligned), the float64 normalisation [kHaloRows][2 nw], then either the
-// float64 best S/N of every halo cell [kHaloRows][kHaloCols] (EXACT) or the screen
-// constants of the inner rows [kSpsRows][nw] (16 bytes each).
+// row is 16-byte aligned), the float64 normalisation [kHaloRows][2 nw], then (EXACT only)
+// the float64 best S/N of every halo cell [kHaloRows][kHaloCols].
 struct DetectLds {
     int nrm, tail, total;   // byte offsets
 };
@@ -133,7 +155,7 @@ __host__ __device__ inline DetectLds detect_lds(int wmax, int nw, bool exact) {
     DetectLds L;
     L.nrm = (8 + kHaloRows * detect_row_stride(wmax) * 4 + 15) / 16 * 16;
     L.tail = L.nrm + kHaloRows * 2 * nw * 8;
-    L.total = L.tail + (exact ? kHaloRows * kHaloCols * 8 : kSpsRows * nw * 16);
+    L.total = L.tail + (exact ? kHaloRows * kHaloCols * 8 : 0);
     return L;
 }
 
@@ -154,22 +176,16 @@ __device__ __forceinline__ double exact_best(const uint32_t* pre, int stride, co
 }
 
 // EXACT: every halo cell in float64 (needed when the best plane is an output).
-// Otherwise a float32 screen runs first. Per row and width it uses the integer centre
-// c = rint(w*mu), the fraction f = w*mu - c and r, so that S/N = (S - c - f) r. The
-// centred sum S - c is exact in int32 (the launcher takes this path only when every
-// window sum is below 2^31), and one fma gives the float32 S/N of each width within
-// 1.5 * 2^-23 (|S/N| + r) of the float64 one. For v32, the float32 best over the widths,
-// the float64 best is then below v32 + 2^-20 (|v32| + max_w r + 1): widths with a
-// negative float32 S/N stay below that bound because the error shrinks as the value
-// grows. Only cells that reach the threshold under this bound are evaluated exactly,
-// together with their 8 neighbours. The peak decision is then the exact float64 rule,
-// and every other cell is certainly below the threshold.
+// Otherwise an integer screen runs first (min_passing_sum): cells whose best S/N cannot
+// reach the threshold are dropped, and only the others, with their 8 neighbours, are
+// evaluated in float64 for the 3x3 peak decision. The launcher takes this path only when
+// every window sum is below 2^31.
 template <bool EXACT>
 __global__ __launch_bounds__(256) void sps_detect_kernel(
     const int32_t* __restrict__ dd, int64_t dd_pitch, int64_t dd_t0, int64_t dd_n, int64_t t_begin,
     int64_t t_end, int64_t t_total, int32_t B, int32_t ndm, double threshold, SpsConst sc,
-    const double* __restrict__ norms, int32_t* __restrict__ rowcount, uint32_t* __restrict__ mask,
-    int64_t nwords, float* __restrict__ best_out, int64_t best_pitch) {
+    const double* __restrict__ norms, const uint32_t* __restrict__ smin_g, int32_t* __restrict__ rowcount,
+    uint32_t* __restrict__ mask, int64_t nwords, float* __restrict__ best_out, int64_t best_pitch) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
     const int nw = sc.nw;
     const int tw = kSpsTile + 1 + sc.wmax;            // D columns t_tile0-1 .. t_tile0+255+wmax
@@ -205,17 +221,54 @@ __global__ __launch_bounds__(256) void sps_detect_kernel(
                           (reinterpret_cast<uintptr_t>(dd) & 15) == 0;
         const int ilo = col0 < 0 ? static_cast<int>(-col0) : 0;
         const int ihi = static_cast<int>(min<int64_t>(tw, dd_n - col0));
-        for (int r = wave; r < kHaloRows; r += 4) {
+        // up to 128 groups (wmax <= 256): all of the wave's loads are issued before any
+        // scan, so their latencies overlap
+        const bool fast2 = fast && nq <= 128;
+        u32x4_t xs[3][2];
+        uint32_t firsts[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            firsts[i] = 0u;
+            xs[i][0] = xs[i][1] = u32x4_t{0u, 0u, 0u, 0u};
+            const int r = wave + 4 * i, d = d0 - 1 + r;
+            if (fast2 && r < kHaloRows && d >= 0 && d < ndm) {
+                const int32_t* src = dd + static_cast<int64_t>(d) * dd_pitch + col0;
+                firsts[i] = static_cast<uint32_t>(src[0]);
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+                    if (64 * c + lane < nq) xs[i][c] = *reinterpret_cast<const u32x4_t*>(src + 1 + 4 * (64 * c + lane));
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const int r = wave + 4 * i;
+            if (r >= kHaloRows) break;
             const int d = d0 - 1 + r;
             const bool in = d >= 0 && d < ndm;
             if (lane < 2 * nw) nrm[r * 2 * nw + lane] = in ? nj[static_cast<int64_t>(d) * (2 * nw) + lane] : 0.0;
             uint32_t* prow = pre + r * ps;
             if (!in) {
-                for (int i = lane; i < ps; i += 64) prow[i] = 0u;
+                for (int k = lane; k < ps; k += 64) prow[k] = 0u;
                 continue;
             }
             const int32_t* src = dd + static_cast<int64_t>(d) * dd_pitch + col0;
-            if (fast) {
+            if (fast2) {
+                uint32_t carry = firsts[i];
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const int u = 64 * c + lane;
+                    const u32x4_t x = xs[i][c];
+                    const uint32_t a = x[0], b = a + x[1], cc = b + x[2], e = cc + x[3];
+                    const uint32_t incl = wave_incl_scan(e);
+                    const uint32_t base = carry + (incl - e);
+                    if (u < nq) *reinterpret_cast<u32x4_t*>(prow + 2 + 4 * u) = u32x4_t{base + a, base + b, base + cc, base + e};
+                    carry += static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(incl), 63));
+                }
+                if (lane == 0) {
+                    prow[0] = 0u;
+                    prow[1] = firsts[i];
+                }
+            } else if (fast) {
                 // lane holds columns t_tile0 + 4u .. + 3, u = lane, lane + 64, ...
                 const uint32_t first = static_cast<uint32_t>(src[0]);
                 uint32_t carry = first;
@@ -250,34 +303,15 @@ __global__ __launch_bounds__(256) void sps_detect_kernel(
             }
         }
     }
-    // screen constants of the inner rows wave + 1 and wave + 5 (lane k holds width k):
-    // {-c, r, -f*r} as int32, float, float, and the row's max r in rm
-    int4* scr = reinterpret_cast<int4*>(smem + L.tail);                  // [kSpsRows][nw]
-    float rm[2] = {0.0f, 0.0f};
+    // screen thresholds of the inner rows wave + 1 and wave + 5 (from the statistics
+    // kernel): lane k holds width k's smallest passing window sum (kNever if none)
+    uint32_t smin[2] = {kNever, kNever};
+    const int wlane = lane < nw ? sc.widths[lane < kMaxWidths ? lane : 0] : 0;   // width of lane k
     if constexpr (!EXACT) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const int ri = wave + 4 * h;
-            const int d = d0 + ri;
-            float rr = 0.0f;
-            if (lane < nw) {
-                double wmu = 0.0, r64 = 0.0;
-                if (d < ndm) {
-                    wmu = nj[static_cast<int64_t>(d) * (2 * nw) + lane];
-                    r64 = nj[static_cast<int64_t>(d) * (2 * nw) + nw + lane];
-                }
-                const double c = __builtin_rint(wmu);
-                rr = static_cast<float>(r64);
-                int4 q;
-                q.x = -static_cast<int32_t>(c);
-                q.y = __float_as_int(rr);
-                q.z = __float_as_int(-(static_cast<float>(wmu - c) * rr));
-                q.w = 0;
-                scr[ri * nw + lane] = q;
-            }
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) rr = fmaxf(rr, __shfl_xor(rr, o, 64));
-            rm[h] = rr;
+            const int d = d0 + wave + 4 * h;
+            if (lane < nw && d < ndm) smin[h] = smin_g[(static_cast<int64_t>(j) * ndm + d) * nw + lane];
         }
     }
     __syncthreads();
@@ -315,40 +349,38 @@ __global__ __launch_bounds__(256) void sps_detect_kernel(
         __syncthreads();
         if (tid < kSpsRows && d0 + tid < ndm && cnt[tid] > 0) atomicAdd(&rowcount[d0 + tid], cnt[tid]);
     } else {
-        // wave w screens inner rows w and w + 4; lane l holds starts 64 q + l, q < 4.
-        // The same lanes take the exact peak test of the cells that pass, so each row's
-        // mask words and count come from one wave.
-        const float thr = static_cast<float>(threshold);
+        // wave w screens inner rows w and w + 4; lane l holds starts 64 q + l, q < 4. A cell
+        // passes if some width's window sum reaches that width's smallest passing sum,
+        // which is exactly the float64 rule best >= threshold. The same lanes take the exact
+        // peak test of the cells that pass, so each row's mask words and count come from
+        // one wave.
 #pragma unroll 1
         for (int h = 0; h < 2; ++h) {
             const int ri = wave + 4 * h, r = ri + 1;
             const int d = d0 + ri;
             if (d >= ndm) break;
             const uint32_t* pr = pre + r * ps + 1 + lane;   // prefix at start tt0 + 64 q + lane
-            const int4* sk = scr + ri * nw;
             uint32_t neg0[4];
-            float v[4];
+            int32_t margin[4];   // max over widths of (window sum - smallest passing sum)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 neg0[q] = 0u - pr[64 * q];
-                v[q] = -__builtin_huge_valf();
+                asm volatile("" : "+v"(neg0[q]));   // keep the sum below a single three-way add
+                margin[q] = INT32_MIN;
             }
+            const int nsm = static_cast<int>(0u - smin[h]);   // lane k: minus width k's threshold
             for (int k = 0; k < nw; ++k) {
-                const int w = sc.widths[k];
-                const int4 c = sk[k];
-                const float rr = __int_as_float(c.y), nfr = __int_as_float(c.z);
+                const int w = __builtin_amdgcn_readlane(wlane, k);
+                const uint32_t nsk = static_cast<uint32_t>(__builtin_amdgcn_readlane(nsm, k));
+                // sum - smin lies in (-2^31, 2^31): sums are below 2^31 and smin <= 2^31
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int32_t dv = static_cast<int32_t>(pr[64 * q + w] + neg0[q] + static_cast<uint32_t>(c.x));
-                    v[q] = fmaxf(v[q], __builtin_fmaf(static_cast<float>(dv), rr, nfr));
-                }
+                for (int q = 0; q < 4; ++q)
+                    margin[q] = max(margin[q], static_cast<int32_t>(pr[64 * q + w] + neg0[q] + nsk));
             }
-            const float slack = rm[h] + 1.0f;
             uint32_t pass = 0;
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                if (tt0 + 64 * q + lane < tile_end && v[q] + 9.5367431640625e-07f * (fabsf(v[q]) + slack) >= thr)   // 2^-20
-                    pass |= 1u << q;
+                if (margin[q] >= 0 && tt0 + 64 * q + lane < tile_end) pass |= 1u << q;
             int pop = 0;
 #pragma unroll 1
             for (int q = 0; q < 4; ++q) {
@@ -460,7 +492,7 @@ __global__ __launch_bounds__(256) void sps_emit_kernel(
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
 struct WorkLayout {
-    size_t norms, rowcount, mask, total;
+    size_t norms, smin, rowcount, mask, total;
     int64_t nblk, ntiles, nwords;
 };
 
@@ -470,7 +502,8 @@ WorkLayout layout(const aa_plan_s* p, int64_t n_starts) {
     L.ntiles = (n_starts + kSpsTile - 1) / kSpsTile;
     L.nwords = L.ntiles * (kSpsTile / 32);
     L.norms = 0;
-    L.rowcount = align256(static_cast<size_t>(L.nblk) * p->ndm * 2 * p->nwidths * sizeof(double));
+    L.smin = align256(static_cast<size_t>(L.nblk) * p->ndm * 2 * p->nwidths * sizeof(double));
+    L.rowcount = L.smin + align256(static_cast<size_t>(L.nblk) * p->ndm * p->nwidths * sizeof(uint32_t));
     L.mask = L.rowcount + align256(static_cast<size_t>(p->ndm) * sizeof(int32_t));
     L.total = L.mask + align256(static_cast<size_t>(p->ndm) * L.nwords * sizeof(uint32_t));
     return L;
@@ -488,6 +521,7 @@ int launch_single_pulse(const aa_plan_s* p, const int32_t* d_dd, int64_t dd_pitc
     const WorkLayout L = layout(p, n);
     uint8_t* w = static_cast<uint8_t*>(d_work);
     double* norms = reinterpret_cast<double*>(w + L.norms);
+    uint32_t* smin = reinterpret_cast<uint32_t*>(w + L.smin);
     int32_t* rowcount = reinterpret_cast<int32_t*>(w + L.rowcount);
     uint32_t* mask = reinterpret_cast<uint32_t*>(w + L.mask);
     SpsConst sc{};
@@ -498,18 +532,19 @@ int launch_single_pulse(const aa_plan_s* p, const int32_t* d_dd, int64_t dd_pitc
         sc.sqrtw[k] = p->sqrtw[k];
     }
     hipLaunchKernelGGL(sps_stats_kernel, dim3(static_cast<unsigned>(L.nblk), static_cast<unsigned>(p->ndm)), dim3(256),
-                       0, stream, d_dd, dd_pitch, dd_t0, t_begin, t_end, p->stat_block, p->ndm, sc, norms, rowcount);
+                       0, stream, d_dd, dd_pitch, dd_t0, t_begin, t_end, p->stat_block, p->ndm, sc,
+                       static_cast<double>(p->threshold), norms, smin, rowcount);
     AA_HIP(hipGetLastError());
     const unsigned rowblocks = static_cast<unsigned>((p->ndm + kSpsRows - 1) / kSpsRows);
     if (L.ntiles * static_cast<int64_t>(rowblocks) > 0x7fffffff)
         return fail(AA_EINVAL, "aa_single_pulse: too many detection tiles for one launch");
-    // the float32 screen needs every window sum below 2^31 (int32 centred sums)
+    // the integer screen compares window sums below 2^31
     const bool screen = !d_best && static_cast<uint64_t>(p->nchan) * 255u * static_cast<uint64_t>(p->wmax) < (1ull << 31);
     const size_t lds = static_cast<size_t>(detect_lds(p->wmax, p->nwidths, !screen).total);
     hipLaunchKernelGGL(screen ? sps_detect_kernel<false> : sps_detect_kernel<true>,
                        dim3(static_cast<unsigned>(L.ntiles), rowblocks), dim3(256), lds, stream,
                        d_dd, dd_pitch, dd_t0, dd_n, t_begin, t_end, t_total, p->stat_block, p->ndm,
-                       static_cast<double>(p->threshold), sc, norms, rowcount, mask, L.nwords, d_best, best_pitch);
+                       static_cast<double>(p->threshold), sc, norms, smin, rowcount, mask, L.nwords, d_best, best_pitch);
     AA_HIP(hipGetLastError());
     hipLaunchKernelGGL(sps_emit_kernel, dim3(static_cast<unsigned>(p->ndm)), dim3(256), 0, stream, d_dd, dd_pitch,
                        dd_t0, t_begin, p->stat_block, p->ndm, sc, norms, rowcount, mask, L.nwords, d_cand, cap,
