@@ -145,27 +145,28 @@ constexpr int kHaloCols = kSpsTile + 2;
 
 // LDS of a detection work-group, in this order: 8 bytes, prefix sums [kHaloRows][ps]
 // (u32, row stride ps >= kSpsTile + 2 + wmax, a multiple of 4, so that entry 2 of every
-// row is 16-byte aligned), the float64 normalisation [kHaloRows][2 nw], then (EXACT only)
-// the float64 best S/N of every halo cell [kHaloRows][kHaloCols].
+// row is 16-byte aligned), then (EXACT only) the float64 best S/N of every halo cell
+// [kHaloRows][kHaloCols]. The float64 normalisation is read from global memory (cached)
+// by the exact evaluations, which only cells passing the screen need.
 struct DetectLds {
-    int nrm, tail, total;   // byte offsets
+    int tail, total;   // byte offsets
 };
 __host__ __device__ inline int detect_row_stride(int wmax) { return 4 * ((kSpsTile + wmax + 3) / 4 + 1); }
 __host__ __device__ inline DetectLds detect_lds(int wmax, int nw, bool exact) {
     DetectLds L;
-    L.nrm = (8 + kHaloRows * detect_row_stride(wmax) * 4 + 15) / 16 * 16;
-    L.tail = L.nrm + kHaloRows * 2 * nw * 8;
+    (void)nw;
+    L.tail = (8 + kHaloRows * detect_row_stride(wmax) * 4 + 15) / 16 * 16;
     L.total = L.tail + (exact ? kHaloRows * kHaloCols * 8 : 0);
     return L;
 }
 
 // Exact value of one halo cell: best S/N over the widths, float64, same operation order
 // as the oracle. -inf outside the range of rows and starts.
-__device__ __forceinline__ double exact_best(const uint32_t* pre, int stride, const double* nrm, const SpsConst& sc,
-                                             int r, int c, bool valid) {
+__device__ __forceinline__ double exact_best(const uint32_t* pre, int stride, const double* nj, int d0,
+                                             const SpsConst& sc, int r, int c, bool valid) {
     if (!valid) return -__builtin_huge_val();
     const uint32_t* pr = pre + r * stride + c;
-    const double* nr = nrm + r * 2 * sc.nw;
+    const double* nr = nj + static_cast<int64_t>(d0 - 1 + r) * (2 * sc.nw);   // halo row r is trial d0 - 1 + r
     double v = 0.0;
     for (int k = 0; k < sc.nw; ++k) {
         const uint32_t s = pr[sc.widths[k]] - pr[0];
@@ -193,7 +194,6 @@ __global__ __launch_bounds__(256) void sps_detect_kernel(
     const int ps = detect_row_stride(sc.wmax);        // row stride of the prefix sums
     const DetectLds L = detect_lds(sc.wmax, nw, EXACT);
     uint32_t* pre = reinterpret_cast<uint32_t*>(smem + 8);               // [kHaloRows][ps]
-    double* nrm = reinterpret_cast<double*>(smem + L.nrm);               // [kHaloRows][2 nw]
 
     // XCD-aware order: each XCD walks consecutive time tiles of a row block, which share
     // their halo columns in its L2
@@ -210,8 +210,8 @@ __global__ __launch_bounds__(256) void sps_detect_kernel(
     const int wave = tid >> 6, lane = tid & 63;
     const double* nj = norms + static_cast<int64_t>(j) * ndm * (2 * nw);
 
-    // halo row r (trial d0 - 1 + r) belongs to wave r % 4: its normalisation, and the
-    // prefix sums of its D columns, pre[r][j] = sum of D[t_tile0 - 1 + i] for i < j
+    // halo row r (trial d0 - 1 + r) belongs to wave r % 4: the prefix sums of its D
+    // columns, pre[r][j] = sum of D[t_tile0 - 1 + i] for i < j
     // (modulo 2^32: every window sum is exact below 2^32), for j < pw
     {
         const int64_t col0 = tt0 - 1 - dd_t0;          // plane column of i = 0
@@ -245,7 +245,6 @@ __global__ __launch_bounds__(256) void sps_detect_kernel(
             if (r >= kHaloRows) break;
             const int d = d0 - 1 + r;
             const bool in = d >= 0 && d < ndm;
-            if (lane < 2 * nw) nrm[r * 2 * nw + lane] = in ? nj[static_cast<int64_t>(d) * (2 * nw) + lane] : 0.0;
             uint32_t* prow = pre + r * ps;
             if (!in) {
                 for (int k = lane; k < ps; k += 64) prow[k] = 0u;
@@ -323,7 +322,7 @@ __global__ __launch_bounds__(256) void sps_detect_kernel(
             const int r = i / kHaloCols, c = i - r * kHaloCols;
             const int d = d0 - 1 + r;
             const int64_t t = tt0 - 1 + c;
-            best[i] = exact_best(pre, ps, nrm, sc, r, c, d >= 0 && d < ndm && t >= lo && t < hi);
+            best[i] = exact_best(pre, ps, nj, d0, sc, r, c, d >= 0 && d < ndm && t >= lo && t < hi);
         }
         __syncthreads();
         // 3x3 peak test for the inner rows, 64 consecutive starts per wave step
@@ -389,7 +388,7 @@ __global__ __launch_bounds__(256) void sps_detect_kernel(
                     auto val = [&](int rr_, int cc) {
                         const int dr = d0 - 1 + rr_;
                         const int64_t tr = tt0 - 1 + cc;
-                        return exact_best(pre, ps, nrm, sc, rr_, cc, dr >= 0 && dr < ndm && tr >= lo && tr < hi);
+                        return exact_best(pre, ps, nj, d0, sc, rr_, cc, dr >= 0 && dr < ndm && tr >= lo && tr < hi);
                     };
                     const int c0 = 64 * q + lane + 1;
                     const double x = val(r, c0);
