@@ -353,33 +353,44 @@ __global__ __launch_bounds__(256) void sps_detect_kernel(
         // which is exactly the float64 rule best >= threshold. The same lanes take the exact
         // peak test of the cells that pass, so each row's mask words and count come from
         // one wave.
+        // both rows in one width loop (row wave + 5 reads the prefix of row wave + 1 if it
+        // is past the last trial; its result is not used)
+        int32_t margin[2][4];   // max over widths of (window sum - smallest passing sum)
+        {
+            const uint32_t* pr0 = pre + (wave + 1) * ps + 1 + lane;   // prefix at start tt0 + 64 q + lane
+            const uint32_t* pr1 = d0 + wave + 4 < ndm ? pre + (wave + 5) * ps + 1 + lane : pr0;
+            uint32_t neg0[2][4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                neg0[0][q] = 0u - pr0[64 * q];
+                neg0[1][q] = 0u - pr1[64 * q];
+                asm volatile("" : "+v"(neg0[0][q]), "+v"(neg0[1][q]));   // keep each sum one three-way add
+                margin[0][q] = margin[1][q] = INT32_MIN;
+            }
+            const int nsm0 = static_cast<int>(0u - smin[0]);   // lane k: minus width k's threshold
+            const int nsm1 = static_cast<int>(0u - smin[1]);
+#pragma unroll 3
+            for (int k = 0; k < nw; ++k) {
+                const int w = __builtin_amdgcn_readlane(wlane, k);
+                const uint32_t nsk0 = static_cast<uint32_t>(__builtin_amdgcn_readlane(nsm0, k));
+                const uint32_t nsk1 = static_cast<uint32_t>(__builtin_amdgcn_readlane(nsm1, k));
+                // sum - smin lies in (-2^31, 2^31): sums are below 2^31 and smin <= 2^31
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    margin[0][q] = max(margin[0][q], static_cast<int32_t>(pr0[64 * q + w] + neg0[0][q] + nsk0));
+                    margin[1][q] = max(margin[1][q], static_cast<int32_t>(pr1[64 * q + w] + neg0[1][q] + nsk1));
+                }
+            }
+        }
 #pragma unroll 1
         for (int h = 0; h < 2; ++h) {
             const int ri = wave + 4 * h, r = ri + 1;
             const int d = d0 + ri;
             if (d >= ndm) break;
-            const uint32_t* pr = pre + r * ps + 1 + lane;   // prefix at start tt0 + 64 q + lane
-            uint32_t neg0[4];
-            int32_t margin[4];   // max over widths of (window sum - smallest passing sum)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                neg0[q] = 0u - pr[64 * q];
-                asm volatile("" : "+v"(neg0[q]));   // keep the sum below a single three-way add
-                margin[q] = INT32_MIN;
-            }
-            const int nsm = static_cast<int>(0u - smin[h]);   // lane k: minus width k's threshold
-            for (int k = 0; k < nw; ++k) {
-                const int w = __builtin_amdgcn_readlane(wlane, k);
-                const uint32_t nsk = static_cast<uint32_t>(__builtin_amdgcn_readlane(nsm, k));
-                // sum - smin lies in (-2^31, 2^31): sums are below 2^31 and smin <= 2^31
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    margin[q] = max(margin[q], static_cast<int32_t>(pr[64 * q + w] + neg0[q] + nsk));
-            }
             uint32_t pass = 0;
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                if (margin[q] >= 0 && tt0 + 64 * q + lane < tile_end) pass |= 1u << q;
+                if ((h ? margin[1][q] : margin[0][q]) >= 0 && tt0 + 64 * q + lane < tile_end) pass |= 1u << q;
             int pop = 0;
 #pragma unroll 1
             for (int q = 0; q < 4; ++q) {
