@@ -418,6 +418,7 @@ __global__ __launch_bounds__(256) void sps_detect_kernel(
 }
 
 // ---- emission -------------------------------------------------------------------
+constexpr int kEmitList = 1024;   // candidates listed per batch in LDS
 __device__ int block_excl_scan(int v, int* total, int* sh) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int incl = v;
@@ -459,40 +460,68 @@ __global__ __launch_bounds__(256) void sps_emit_kernel(
     if (mine == 0 || off >= cap) return;
     const int32_t* row = dd + static_cast<int64_t>(d) * dd_pitch - dd_t0;
     int64_t running = off;
+    __shared__ int64_t tl[kEmitList];   // starts of one batch of the row's candidates, in order
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int64_t k0 = 0; k0 < nwords; k0 += 256) {
         const int64_t k = k0 + threadIdx.x;
-        uint32_t word = k < nwords ? mask[static_cast<int64_t>(d) * nwords + k] : 0u;
+        const uint32_t word = k < nwords ? mask[static_cast<int64_t>(d) * nwords + k] : 0u;
         int total;
         const int excl = block_excl_scan(__popc(word), &total, sh);
-        int64_t pos = running + excl;
-        while (word) {
-            const int b = __ffs(word) - 1;
-            word &= word - 1;
-            if (pos < cap) {
-                const int64_t t = t_begin + 32 * k + b;
+        for (int b0 = 0; b0 < total; b0 += kEmitList) {
+            // list the batch's starts, then one wave per candidate
+            uint32_t wv = word;
+            for (int idx = excl; wv; ++idx) {
+                const int b = __ffs(wv) - 1;
+                wv &= wv - 1;
+                if (idx >= b0 && idx < b0 + kEmitList) tl[idx - b0] = t_begin + 32 * k + b;
+            }
+            __syncthreads();
+            const int nb = min(kEmitList, total - b0);
+            for (int i = wave; i < nb && running + b0 + i < cap; i += 4) {
+                const int64_t t = tl[i];
                 const int jb = static_cast<int>((t - t_begin) / B);
                 const double* nr = norms + (static_cast<int64_t>(jb) * ndm + d) * (2 * sc.nw);
-                uint32_t s = 0;
-                int i = 0;
+                // window sums from a wave scan: lane l holds samples c0 + 4 l .. c0 + 4 l + 3
+                // of each 256-sample chunk; S/N and the smallest best width in the order
+                // of the detection's exact evaluation
                 double v = 0.0;
                 int wbest = sc.widths[0];
-                for (int q = 0; q < sc.nw; ++q) {
-                    for (; i < sc.widths[q]; ++i) s += static_cast<uint32_t>(row[t + i]);
-                    const double snr = (static_cast<double>(s) - nr[q]) * nr[sc.nw + q];
-                    if (q == 0 || snr > v) {
-                        v = snr;
-                        wbest = sc.widths[q];
+                uint32_t carry = 0;
+                int q = 0;
+                for (int c0 = 0; c0 < sc.wmax; c0 += 256) {
+                    uint32_t x[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int ix = c0 + 4 * lane + e;
+                        x[e] = ix < sc.wmax ? static_cast<uint32_t>(row[t + ix]) : 0u;
                     }
+                    const uint32_t p1 = x[0] + x[1], p2 = p1 + x[2], p3 = p2 + x[3];
+                    const uint32_t incl = wave_incl_scan(p3);
+                    const uint32_t base = carry + (incl - p3);
+                    const uint32_t pre4[4] = {base + x[0], base + p1, base + p2, base + p3};
+                    for (; q < sc.nw && sc.widths[q] <= c0 + 256; ++q) {
+                        const int ix = sc.widths[q] - 1 - c0;    // sum of the first widths[q] samples
+                        const uint32_t sel = pre4[ix & 3];
+                        const uint32_t S = static_cast<uint32_t>(__shfl(static_cast<int>(sel), ix >> 2, 64));
+                        const double snr = (static_cast<double>(S) - nr[q]) * nr[sc.nw + q];
+                        if (q == 0 || snr > v) {
+                            v = snr;
+                            wbest = sc.widths[q];
+                        }
+                    }
+                    carry += static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(incl), 63));
                 }
-                aa_candidate_t c;
-                c.dm_idx = d;
-                c.width = wbest;
-                c.t = t;
-                c.snr = static_cast<float>(v);
-                c.beam = beam_id;
-                cand[pos] = c;
+                if (lane == 0) {
+                    aa_candidate_t c;
+                    c.dm_idx = d;
+                    c.width = wbest;
+                    c.t = t;
+                    c.snr = static_cast<float>(v);
+                    c.beam = beam_id;
+                    cand[running + b0 + i] = c;
+                }
             }
-            ++pos;
+            __syncthreads();
         }
         running += total;
         if (running >= cap) break;
