@@ -68,7 +68,7 @@ def _cpu_triple(centre):
 def cpu_baseline(w, x, n_centres=10):
     """Time the oracle (as it is) on a bounded sample: `n_centres` DM trials spread evenly
     over the plan (every ndm / n_centres-th), each searched over the full time range with
-    its two neighbour rows dedispersed as well. The triples run in a process pool over the
+    its two neighbour rows dedispersed as well. The triples run in a thread pool over the
     host's cores (at most 16 threads); numpy is single-threaded here. value counts only the
     searched centre rows. Threads, not processes: the oracle's large numpy operations
     release the GIL, and no process forks after the GPU is initialised."""
