@@ -21,6 +21,7 @@
 
 #include "aa_internal.h"
 #include "numerics.h"
+#include "screen.h"
 #include "xcd.h"
 
 namespace aa {
@@ -55,24 +56,6 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
-}
-
-// Screen threshold of one (row, width): the smallest window sum S in [0, 2^31) whose
-// S/N, computed as in exact_best, reaches the threshold. The S/N is non-decreasing in S
-// for r >= 0 (each float64 operation is monotone), so a cell's best S/N reaches the
-// threshold exactly when some width's sum reaches its threshold. The search starts at
-// the real crossing point and steps to the exact boundary; if it does not settle within
-// a few steps the threshold errs low (0), which only lets more cells through.
-constexpr uint32_t kNever = 0x80000000u;   // above every window sum on this path
-__device__ __forceinline__ uint32_t min_passing_sum(double wmu, double r, double threshold) {
-    auto reaches = [&](int64_t S) { return (static_cast<double>(S) - wmu) * r >= threshold; };
-    if (!(r > 0.0)) return (0.0 >= threshold) ? 0u : kNever;   // r = 0: every S/N is 0
-    const double x = wmu + threshold / r;
-    int64_t s = x <= 0.0 ? 0 : (x >= 2147483648.0 ? static_cast<int64_t>(kNever) : static_cast<int64_t>(__builtin_ceil(x)));
-    for (int i = 0; i < 16 && s > 0 && reaches(s - 1); ++i) --s;
-    if (s > 0 && reaches(s - 1)) return 0u;
-    for (int i = 0; i < 16 && s < static_cast<int64_t>(kNever) && !reaches(s); ++i) ++s;
-    return static_cast<uint32_t>(s);
 }
 
 // ---- statistics -------------------------------------------------------------
