@@ -6,7 +6,8 @@ The whole plane (3000 x 1,012,255 int32, 12 GB) is beyond the oracle, so the
 oracle checks sampled outputs, each computed on its own:
   * dedispersion: random (trial, sample) pairs, every trial at the first and last
     samples and at a random one, and full 32768-sample runs of a few trials, for
-    the autotuned variant and for each kernel family;
+    the autotuned variant, every matrix-core variant and one variant of each other
+    kernel family;
   * candidates: regions of one trial x one statistics block, where the oracle
     dedisperses the trial and its two neighbours over the block (plus boxcar and
     peak halo) and runs its own search. Regions are those of the strongest GPU
@@ -84,10 +85,14 @@ def test_survey_dedisp_sampled(survey):
     say(f"  autotune ms per variant {['%.1f' % m for m in ms]} -> variant {plan.variant}")
     chosen = plan.variant
     _check_plane(sv, dd, rng)
+    # every matrix-core variant (any of them can be the autotuner's pick), and the first
+    # variant of each other layout
+    check = {v for v, info in enumerate(Plan.variants()) if info["layout"] in (4, 5)}
     layouts = {}
     for v, info in enumerate(Plan.variants()):
         layouts.setdefault(info["layout"], v)
-    for v in sorted(set(layouts.values()) - {chosen}):
+    check |= set(layouts.values())
+    for v in sorted(check - {chosen}):
         say(f"  variant {v}")
         plan.set_variant(v)
         dd.fill_(-1)
