@@ -436,7 +436,7 @@ def main():
     value = ndm * n_dd / (ms_step * 1e-3)
     vinfo = Plan.variants()[plan.variant]
     traffic = TRAFFIC_BYTES.get((w["name"], plan.variant)) if not a.ndm else None
-    if vinfo["layout"] in (4, 5):
+    if vinfo["layout"] in (4, 5, 6):
         # a contraction on the i8 matrix cores, priced against their dense peak; one op
         # per useful byte add (the one-hot weights are not counted)
         roofline = {"bound": "mfma", "dtype": "i8", "kernel": "dedisp_kernel (i8 matrix cores)",

@@ -139,10 +139,11 @@ typedef struct {
     int32_t id, waves, dm_per_wave, trials_per_block, lds_bytes;
     int32_t layout;   /* 0, 3: a lane owns 16 contiguous samples; 1, 2: four groups of 4, 256 apart
                          (2 reuses a window when the next trial has the same offset);
-                         4: i8 matrix-core contraction over an exact split of the shift table */
+                         4, 5: i8 matrix-core contraction over an exact split of the shift table
+                         (4 or 8 channels per step); 6: both, chosen per block of trials */
     int32_t time_tile;   /* output samples per work-group */
     int32_t depth;       /* staging buffers per work-group (loads run depth - 1 passes ahead) */
-    int32_t max_tiles;   /* layout 4: a channel block spans at most 32 * max_tiles rows of the
+    int32_t max_tiles;   /* layouts 4-6: a channel block spans at most 32 * max_tiles rows of the
                             shifted time axis (31 or 63); 0 for the other layouts */
 } aa_variant_t;
 

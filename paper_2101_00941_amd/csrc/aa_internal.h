@@ -40,11 +40,12 @@ struct DedispVariant {
                      // 4: matrix-core contraction (v_mfma_i32_32x32x32_i8), 4 channels x 8
                      //    residuals per step, see below
                      // 5: the same contraction with 8 channels x 4 residuals per step
+                     // 6: layouts 5 and 4 mixed by trial range (per DM block)
     int tile;        // output samples per work-group (time tile)
     int depth;       // staging buffers in the LDS ring (loads run depth - 1 steps ahead)
     int max_tiles;   // layout 4: a channel block spans at most 32 * max_tiles rows of t' (31 or 63)
 };
-constexpr int kNumDedispVariants = 20;
+constexpr int kNumDedispVariants = 21;
 
 // Matrix-core variant (layout 4). Within a block of up to 32 trials (first trial d0)
 // and a run of channels, the shift splits exactly as
@@ -58,7 +59,8 @@ constexpr int kNumDedispVariants = 20;
 // 32/CPS.
 // A channel block spans at most 32 * max_tiles rows of t', with max_tiles 63 or 31. A
 // staged row then needs at most 32 * max_tiles + 26 bytes: 2048 or 1024 bytes of LDS.
-constexpr int mfma_cps(int layout) { return layout == 5 ? 8 : 4; }
+// Layout 6 takes the step shape per DM block (DmBlock::cps); mfma_cps is 0 for it.
+constexpr int mfma_cps(int layout) { return layout == 5 ? 8 : layout == 6 ? 0 : 4; }
 constexpr int mfma_row_bytes(int max_tiles) { return max_tiles <= 31 ? 1024 : 2048; }
 // Record of one DM block and step k (D = the variant's depth), CPS channels per step:
 //   [0, 32 CPS)   u8  8*r[d][CPS k + i] at CPS d + i (d < 32, i < CPS)
@@ -92,8 +94,10 @@ struct DmBlock {
     int32_t first;   // first DM trial of the block
     int32_t count;   // trials in the block (<= waves * dpw)
     int32_t row;     // LDS row length (bytes) the block needs, multiple of 16 (layouts 0-3)
-    int32_t rs_lo;   // layout 4: smallest and largest staged-row start over the block's
+    int32_t rs_lo;   // layouts 4-6: smallest and largest staged-row start over the block's
     int32_t rs_hi;   // channels, relative to the time tile (0 for the other layouts)
+    int32_t cps;     // layouts 4-6: channels per matrix step of this block (4 or 8)
+    int32_t rec256;  // layouts 4-6: offset of the block's records in 256-byte units
 };
 
 // Per-variant tables. For block b and channel c:
@@ -153,8 +157,10 @@ int prepare_variant(aa_plan_s* p, int variant);
 // Host tables of the matrix-core variants: DM blocks, 16-aligned staged-row starts
 // [nblk][nchan_pad] and the per-step records [nblk][nchan_pad / cps][record size], with
 // nchan_pad = nchan rounded up to cps channels.
+// cps 4 or 8: one step shape; cps 0: 8 channels per step below a split trial and 4 from
+// it on, the split taken from a cost estimate, or split_at when that is >= 0.
 int build_mfma_tables(const aa_plan_s* p, int tile, int depth, int max_tiles, int cps, std::vector<DmBlock>& blocks,
-                      std::vector<int32_t>& rsv, std::vector<uint8_t>& rec);
+                      std::vector<int32_t>& rsv, std::vector<uint8_t>& rec, int split_at = -1);
 void free_tables(DedispTables& t);
 // Launchers (dedisp.hip, sps.hip). Arguments are validated by the callers.
 int launch_dedisperse(const aa_plan_s* p, int variant, const uint8_t* d_in, int64_t in_pitch, int64_t n_in,

@@ -609,7 +609,7 @@ __device__ __forceinline__ void dedisp_mfma_tile(const DedispArgs& A, int blk, i
     cx.t0 = t0;
     cx.last16 = A.n_in16 - 16;
     cx.K = A.nchan_pad / CPS;
-    cx.recg = reinterpret_cast<const uint8_t*>(A.offs) + static_cast<int64_t>(blk) * cx.K * L::RL.size;
+    cx.recg = reinterpret_cast<const uint8_t*>(A.offs) + static_cast<int64_t>(A.blocks[blk].rec256) * 256;
     const int tid = threadIdx.x;
     cx.wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     cx.lane = tid & 63;
@@ -695,12 +695,23 @@ __device__ __forceinline__ void dedisp_mfma_tile(const DedispArgs& A, int blk, i
     }
 }
 
+// Layout 6: the DM block's own step shape (the whole work-group takes one branch).
+template <int W, int TILE, int DEPTH, int MAXT>
+__device__ __forceinline__ void dedisp_mfma_mixed(const DedispArgs& A, int blk, int64_t t0) {
+    if (__builtin_amdgcn_readfirstlane(A.blocks[blk].cps) == 8)
+        dedisp_mfma_tile<W, TILE, DEPTH, MAXT, 8>(A, blk, t0);
+    else
+        dedisp_mfma_tile<W, TILE, DEPTH, MAXT, 4>(A, blk, t0);
+}
+
 // WPE: waves per SIMD the register allocation must allow (2 work-groups per CU for the
 // 80 KB matrix-core variants).
 template <int DPW, int W, int LAYOUT, int TILE = kTimeTile, int DEPTH = 2, int MAXT = 63, int WPE = 1>
 __global__ __launch_bounds__(64 * W, WPE) void dedisp_kernel(DedispArgs a) {
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
-    if constexpr (LAYOUT == 4 || LAYOUT == 5)
+    if constexpr (LAYOUT == 6)
+        dedisp_mfma_mixed<W, TILE, DEPTH, MAXT>(a, bid % a.nblk, static_cast<int64_t>(bid / a.nblk) * TILE);
+    else if constexpr (LAYOUT == 4 || LAYOUT == 5)
         dedisp_mfma_tile<W, TILE, DEPTH, MAXT, mfma_cps(LAYOUT)>(a, bid % a.nblk, static_cast<int64_t>(bid / a.nblk) * TILE);
     else
         dedisp_tile<DPW, W, LAYOUT>(a, bid % a.nblk, static_cast<int64_t>(bid / a.nblk) * kTimeTile);
@@ -734,7 +745,9 @@ __global__ __launch_bounds__(64 * W, WPE) void dedisp_batch_kernel(const DedispA
         }
         const DedispArgs a = args[lo];
         const int64_t local = it - item_begin[lo];
-        if constexpr (LAYOUT == 4 || LAYOUT == 5)
+        if constexpr (LAYOUT == 6)
+            dedisp_mfma_mixed<W, TILE, DEPTH, MAXT>(a, static_cast<int>(local % a.nblk), (local / a.nblk) * TILE);
+        else if constexpr (LAYOUT == 4 || LAYOUT == 5)
             dedisp_mfma_tile<W, TILE, DEPTH, MAXT, mfma_cps(LAYOUT)>(a, static_cast<int>(local % a.nblk),
                                                                      (local / a.nblk) * TILE);
         else
@@ -754,7 +767,7 @@ typedef void (*DedispBatchFn)(const DedispArgs*, const int64_t*, int, int64_t, u
     K<4, 4, 1>, K<2, 8, 1>, K<4, 8, 1>, K<2, 16, 1>, K<2, 8, 0>, K<4, 4, 0>, K<2, 8, 3>, K<4, 4, 3>, \
         K<2, 8, 2>, K<4, 8, 2>, K<4, 4, 2>, K<4, 8, 4, 1024, 3>, K<2, 16, 4, 1024, 3>, K<2, 16, 4, 768, 7>, \
         K<4, 8, 4, 512, 3, 31, 4>, K<2, 16, 4, 512, 3, 31, 8>, K<4, 8, 4, 480, 4, 31, 4>, K<2, 16, 5, 864, 3, 63>, \
-        K<2, 16, 4, 960, 4, 63>, K<2, 16, 4, 896, 5, 63>
+        K<2, 16, 4, 960, 4, 63>, K<2, 16, 4, 896, 5, 63>, K<2, 16, 6, 864, 3, 63>
 const DedispFn kKernels[kNumDedispVariants] = {AA_VARIANTS(dedisp_kernel)};
 const DedispBatchFn kBatchKernels[kNumDedispVariants] = {AA_VARIANTS(dedisp_batch_kernel)};
 #undef AA_VARIANTS

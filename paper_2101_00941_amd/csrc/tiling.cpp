@@ -36,6 +36,8 @@ const DedispVariant kDedispVariants[kNumDedispVariants] = {
     // deeper staging rings (loads 3 or 4 steps ahead) for slightly smaller tiles
     {18, 16, 2, mfma_lds_bytes(960, 4, 63), 4, 960, 4, 63},     // 1024 threads, 4 tiles per wave
     {19, 16, 2, mfma_lds_bytes(896, 5, 63), 4, 896, 5, 63},     // 1024 threads, 4 tiles per wave
+    // step shape per DM block: 8 x 4 below a split trial, 4 x 8 above it
+    {20, 16, 2, mfma_lds_bytes(864, 3, 63, 8), 6, 864, 3, 63},  // 1024 threads, 4 tiles per wave
 };
 
 void free_tables(DedispTables& t) {
@@ -55,7 +57,7 @@ int upload(T** dst, const std::vector<T>& src) {
 }
 }  // namespace
 
-// Tables of the matrix-core variants (layouts 4 and 5). f(d, c) = s[d][c] - s[d0][c];
+// Tables of the matrix-core variants (layouts 4, 5 and 6). f(d, c) = s[d][c] - s[d0][c];
 // a step is `cps` consecutive channels and R = 32 / cps is the residual range.
 //  * DM blocks: up to 32 consecutive trials such that every step on its own has a
 //    residual range below R (so a channel block always holds at least one step) and,
@@ -69,125 +71,203 @@ int upload(T** dst, const std::vector<T>& src) {
 //  * Padded channels (c >= nchan) are staged from a row of 0x80 bytes, which the kernel
 //    maps to 0, so their residuals are 0. Absent trials of a short block have r = 0,
 //    e = 0 and are not written out.
-int build_mfma_tables(const aa_plan_s* p, int tile, int depth, int max_tiles, int cps, std::vector<DmBlock>& blocks,
-                      std::vector<int32_t>& rsv, std::vector<uint8_t>& rec) {
-    const int nchan = p->nchan;
-    if (cps != 4 && cps != 8) return fail(AA_EINVAL, "matrix-core tiling: 4 or 8 channels per step");
-    const int R = 32 / cps;
-    const int npad = (nchan + cps - 1) / cps * cps;
-    const int K = npad / cps;
-    const MfmaRec RL = mfma_rec(cps);
-    const int spread_max = max_tiles * 32 - tile;
-    const int row = mfma_row_bytes(max_tiles);
-    if (tile % 32 || tile < 256 || spread_max < 0 || depth < 3 || (max_tiles != 31 && max_tiles != 63))
-        return fail(AA_EINVAL, "matrix-core tiling: bad tile, depth or channel-block span");
+//  * Layout 6 mixes the two step shapes by trial range: blocks below a split trial use
+//    8 channels x 4 residuals, the others 4 x 8. Each block records its shape and where
+//    its records start.
+namespace {
+
+struct MfmaGeom {
+    int tile, depth, max_tiles, spread_max, row;
+};
+
+// Trials of the block that starts at d0 under the cps rules.
+int grow_block(const aa_plan_s* p, int d0, int cps, const MfmaGeom& g, std::vector<int32_t>& fmin,
+               std::vector<int32_t>& fmax) {
+    const int nchan = p->nchan, R = 32 / cps;
     auto S = [&](int d, int c) { return p->shifts[static_cast<size_t>(d) * nchan + c]; };
-    blocks.clear();
-    std::vector<int32_t> fmin(nchan), fmax(nchan);
-    for (int d0 = 0; d0 < p->ndm;) {
-        std::fill(fmin.begin(), fmin.end(), 0);
-        std::fill(fmax.begin(), fmax.end(), 0);
-        int count = 1;
-        while (count < 32 && d0 + count < p->ndm) {
-            const int d = d0 + count;
+    std::fill(fmin.begin(), fmin.end(), 0);
+    std::fill(fmax.begin(), fmax.end(), 0);
+    int count = 1;
+    while (count < 32 && d0 + count < p->ndm) {
+        const int d = d0 + count;
+        bool ok = true;
+        for (int c0 = 0; c0 < nchan && ok; c0 += cps) {
+            int lo = INT32_MAX, hi = INT32_MIN;
+            for (int c = c0; c < std::min(c0 + cps, nchan); ++c) {
+                const int32_t f = S(d, c) - S(d0, c);
+                lo = std::min(lo, f);
+                hi = std::max(hi, f);
+                if (std::max(fmax[c], f) - std::min(fmin[c], f) > g.spread_max) ok = false;
+            }
+            if (hi - lo > R - 1) ok = false;
+        }
+        if (!ok) break;
+        for (int c = 0; c < nchan; ++c) {
+            const int32_t f = S(d, c) - S(d0, c);
+            fmin[c] = std::min(fmin[c], f);
+            fmax[c] = std::max(fmax[c], f);
+        }
+        ++count;
+    }
+    return count;
+}
+
+// Row starts (npad entries) and records (npad / cps of them) of one block; `work` gets the
+// block's tile-steps (one matrix op per 32-row tile and step) and flushed tiles per time tile.
+int block_tables(const aa_plan_s* p, DmBlock& blk, int cps, const MfmaGeom& g, int npad, int32_t* rsv, uint8_t* Rb,
+                 int64_t* mfma_tiles, int64_t* flush_tiles) {
+    const int nchan = p->nchan, R = 32 / cps, K = npad / cps;
+    const MfmaRec RL = mfma_rec(cps);
+    auto S = [&](int d, int c) { return p->shifts[static_cast<size_t>(d) * nchan + c]; };
+    const int d0 = blk.first, count = blk.count;
+    std::vector<int32_t> lo(32), hi(32);
+    int64_t mt = 0, ft = 0;
+    for (int k0 = 0; k0 < K;) {
+        // grow the channel block [k0, k1) step by step
+        std::fill(lo.begin(), lo.end(), INT32_MAX);
+        std::fill(hi.begin(), hi.end(), INT32_MIN);
+        int k1 = k0;
+        while (k1 < K) {
             bool ok = true;
-            for (int c0 = 0; c0 < nchan && ok; c0 += cps) {
-                int lo = INT32_MAX, hi = INT32_MIN;
-                for (int c = c0; c < std::min(c0 + cps, nchan); ++c) {
-                    const int32_t f = S(d, c) - S(d0, c);
-                    lo = std::min(lo, f);
-                    hi = std::max(hi, f);
-                    if (std::max(fmax[c], f) - std::min(fmin[c], f) > spread_max) ok = false;
+            for (int i = 0; i < count && ok; ++i) {
+                int l = lo[i], h = hi[i];
+                for (int c = cps * k1; c < std::min(cps * k1 + cps, nchan); ++c) {
+                    const int32_t f = S(d0 + i, c) - S(d0, c);
+                    l = std::min(l, f);
+                    h = std::max(h, f);
                 }
-                if (hi - lo > R - 1) ok = false;
+                if (h - l > R - 1) ok = false;
             }
             if (!ok) break;
-            for (int c = 0; c < nchan; ++c) {
-                const int32_t f = S(d, c) - S(d0, c);
-                fmin[c] = std::min(fmin[c], f);
-                fmax[c] = std::max(fmax[c], f);
-            }
-            ++count;
+            for (int i = 0; i < count; ++i)
+                for (int c = cps * k1; c < std::min(cps * k1 + cps, nchan); ++c) {
+                    const int32_t f = S(d0 + i, c) - S(d0, c);
+                    lo[i] = std::min(lo[i], f);
+                    hi[i] = std::max(hi[i], f);
+                }
+            ++k1;
         }
-        blocks.push_back(DmBlock{d0, count, 0, 0, 0});
+        if (k1 == k0) return fail(AA_EINVAL, "matrix-core tiling: a step exceeds the residual range");
+        int32_t emin = INT32_MAX, emax = INT32_MIN;
+        for (int i = 0; i < count; ++i) {
+            emin = std::min(emin, lo[i]);
+            emax = std::max(emax, lo[i]);
+        }
+        const int tiles = (emax - emin + g.tile + 31) / 32;
+        if (tiles > g.max_tiles) return fail(AA_EINVAL, "matrix-core tiling: channel block spread too large");
+        mt += static_cast<int64_t>(tiles) * (k1 - k0);
+        ft += tiles;
+        for (int k = k0; k < k1; ++k) {
+            uint8_t* rk = Rb + static_cast<size_t>(k) * RL.size;
+            for (int j = 0; j < cps; ++j) {
+                const int c = cps * k + j;
+                const int32_t v = c < nchan ? S(d0, c) + emin : 0;
+                rsv[c] = v & ~15;
+                rk[RL.phase + j] = static_cast<uint8_t>(v & 15);
+                for (int i = 0; i < count && c < nchan; ++i) {
+                    const int32_t r = S(d0 + i, c) - S(d0, c) - lo[i];
+                    rk[cps * i + j] = static_cast<uint8_t>(8 * r);
+                }
+            }
+            for (int i = 0; i < count; ++i) {
+                const int16_t e = static_cast<int16_t>(lo[i] - emin);
+                std::memcpy(rk + RL.e + 2 * i, &e, 2);
+            }
+            const int32_t left = k1 - k, emax_rel = emax - emin;
+            std::memcpy(rk + RL.tiles, &tiles, 4);
+            std::memcpy(rk + RL.left, &left, 4);
+            std::memcpy(rk + RL.max_e, &emax_rel, 4);
+        }
+        k0 = k1;
+    }
+    blk.rs_lo = *std::min_element(rsv, rsv + npad);
+    blk.rs_hi = *std::max_element(rsv, rsv + npad);
+    // row starts and lengths of step k + depth - 1, read by the kernel when it issues
+    // that step's loads. A row needs the bytes [0, 32 tiles + phase + 11).
+    for (int k = 0; k + g.depth - 1 < K; ++k) {
+        uint8_t* rk = Rb + static_cast<size_t>(k) * RL.size;
+        const uint8_t* rn = Rb + static_cast<size_t>(k + g.depth - 1) * RL.size;
+        std::memcpy(rk + RL.next_rs, &rsv[cps * (k + g.depth - 1)], 4 * cps);
+        int32_t tiles;
+        std::memcpy(&tiles, rn + RL.tiles, 4);
+        const int32_t need = std::min(g.row / 16, (32 * tiles + 15 + 11 + 15) / 16);
+        std::memcpy(rk + RL.next_need, &need, 4);
+    }
+    if (mfma_tiles) *mfma_tiles = mt;
+    if (flush_tiles) *flush_tiles = ft;
+    return AA_OK;
+}
+
+// Relative cost of a block's work per time tile on MI355X, fitted to the measured
+// survey launches of the two step shapes (254 and 255 ms): a flushed tile costs about
+// 4.2 tile-steps (the flush plus the per-run overhead).
+constexpr double kFlushPerTileStep = 4.2;
+
+}  // namespace
+
+int build_mfma_tables(const aa_plan_s* p, int tile, int depth, int max_tiles, int cps, std::vector<DmBlock>& blocks,
+                      std::vector<int32_t>& rsv, std::vector<uint8_t>& rec, int split_at) {
+    const int nchan = p->nchan;
+    if (cps != 4 && cps != 8 && cps != 0) return fail(AA_EINVAL, "matrix-core tiling: 4, 8 or mixed channels per step");
+    MfmaGeom g{tile, depth, max_tiles, max_tiles * 32 - tile, mfma_row_bytes(max_tiles)};
+    if (tile % 32 || tile < 256 || g.spread_max < 0 || depth < 3 || (max_tiles != 31 && max_tiles != 63))
+        return fail(AA_EINVAL, "matrix-core tiling: bad tile, depth or channel-block span");
+    const int npad = (nchan + (cps == 4 ? 3 : 7)) / (cps == 4 ? 4 : 8) * (cps == 4 ? 4 : 8);
+    std::vector<int32_t> fmin(nchan), fmax(nchan);
+    // block shapes: the split trial below which blocks use 8 channels per step
+    int split = cps == 8 ? p->ndm : 0;
+    if (cps == 0 && split_at >= 0) {
+        split = std::min(split_at, p->ndm);
+    } else if (cps == 0) {
+        // price each shape's own partition, then take the split (at an 8-channel block
+        // boundary) that minimises the estimated cost
+        std::vector<int32_t> rsv_tmp(npad);
+        std::vector<std::pair<int, double>> c8, c4;   // (first trial, cost)
+        for (int shape : {8, 4}) {
+            std::vector<uint8_t> rec_tmp(static_cast<size_t>(npad / shape) * mfma_rec(shape).size);
+            for (int d0 = 0; d0 < p->ndm;) {
+                DmBlock b{d0, grow_block(p, d0, shape, g, fmin, fmax), 0, 0, 0, shape, 0};
+                int64_t mt = 0, ft = 0;
+                const int rc = block_tables(p, b, shape, g, npad, rsv_tmp.data(), rec_tmp.data(), &mt, &ft);
+                if (rc != AA_OK) return rc;
+                (shape == 8 ? c8 : c4).push_back({d0, static_cast<double>(mt) + kFlushPerTileStep * static_cast<double>(ft)});
+                d0 += b.count;
+            }
+        }
+        double best = -1.0;
+        for (size_t i = 0; i <= c8.size(); ++i) {
+            const int d = i < c8.size() ? c8[i].first : p->ndm;
+            double cost = 0.0;
+            for (size_t k = 0; k < i; ++k) cost += c8[k].second;
+            for (const auto& b : c4)
+                if (b.first >= d) cost += b.second;
+            if (best < 0.0 || cost < best) {
+                best = cost;
+                split = d;
+            }
+        }
+    }
+    blocks.clear();
+    for (int d0 = 0; d0 < p->ndm;) {
+        const int shape = d0 < split ? 8 : 4;
+        int count = grow_block(p, d0, shape, g, fmin, fmax);
+        if (shape == 8 && d0 + count > split) count = split - d0;   // the 4-channel part starts at the split
+        blocks.push_back(DmBlock{d0, count, 0, 0, 0, shape, 0});
         d0 += count;
     }
     const size_t nblk = blocks.size();
+    size_t rec_bytes = 0;
+    for (auto& b : blocks) {
+        b.rec256 = static_cast<int32_t>(rec_bytes / 256);
+        rec_bytes += static_cast<size_t>(npad / b.cps) * mfma_rec(b.cps).size;
+    }
     rsv.assign(nblk * npad, 0);
-    rec.assign(nblk * K * RL.size, 0);
-    std::vector<int32_t> lo(32), hi(32);
+    rec.assign(rec_bytes, 0);
     for (size_t bi = 0; bi < nblk; ++bi) {
-        const int d0 = blocks[bi].first, count = blocks[bi].count;
-        uint8_t* Rb = &rec[bi * K * RL.size];
-        for (int k0 = 0; k0 < K;) {
-            // grow the channel block [k0, k1) step by step
-            std::fill(lo.begin(), lo.end(), INT32_MAX);
-            std::fill(hi.begin(), hi.end(), INT32_MIN);
-            int k1 = k0;
-            while (k1 < K) {
-                bool ok = true;
-                for (int i = 0; i < count && ok; ++i) {
-                    int l = lo[i], h = hi[i];
-                    for (int c = cps * k1; c < std::min(cps * k1 + cps, nchan); ++c) {
-                        const int32_t f = S(d0 + i, c) - S(d0, c);
-                        l = std::min(l, f);
-                        h = std::max(h, f);
-                    }
-                    if (h - l > R - 1) ok = false;
-                }
-                if (!ok) break;
-                for (int i = 0; i < count; ++i)
-                    for (int c = cps * k1; c < std::min(cps * k1 + cps, nchan); ++c) {
-                        const int32_t f = S(d0 + i, c) - S(d0, c);
-                        lo[i] = std::min(lo[i], f);
-                        hi[i] = std::max(hi[i], f);
-                    }
-                ++k1;
-            }
-            if (k1 == k0) return fail(AA_EINVAL, "matrix-core tiling: a step exceeds the residual range");
-            int32_t emin = INT32_MAX, emax = INT32_MIN;
-            for (int i = 0; i < count; ++i) {
-                emin = std::min(emin, lo[i]);
-                emax = std::max(emax, lo[i]);
-            }
-            const int tiles = (emax - emin + tile + 31) / 32;
-            if (tiles > max_tiles) return fail(AA_EINVAL, "matrix-core tiling: channel block spread too large");
-            for (int k = k0; k < k1; ++k) {
-                uint8_t* rk = Rb + static_cast<size_t>(k) * RL.size;
-                for (int j = 0; j < cps; ++j) {
-                    const int c = cps * k + j;
-                    const int32_t v = c < nchan ? S(d0, c) + emin : 0;
-                    rsv[bi * npad + c] = v & ~15;
-                    rk[RL.phase + j] = static_cast<uint8_t>(v & 15);
-                    for (int i = 0; i < count && c < nchan; ++i) {
-                        const int32_t r = S(d0 + i, c) - S(d0, c) - lo[i];
-                        rk[cps * i + j] = static_cast<uint8_t>(8 * r);
-                    }
-                }
-                for (int i = 0; i < count; ++i) {
-                    const int16_t e = static_cast<int16_t>(lo[i] - emin);
-                    std::memcpy(rk + RL.e + 2 * i, &e, 2);
-                }
-                const int32_t left = k1 - k, emax_rel = emax - emin;
-                std::memcpy(rk + RL.tiles, &tiles, 4);
-                std::memcpy(rk + RL.left, &left, 4);
-                std::memcpy(rk + RL.max_e, &emax_rel, 4);
-            }
-            k0 = k1;
-        }
-        blocks[bi].rs_lo = *std::min_element(rsv.begin() + bi * npad, rsv.begin() + (bi + 1) * npad);
-        blocks[bi].rs_hi = *std::max_element(rsv.begin() + bi * npad, rsv.begin() + (bi + 1) * npad);
-        // row starts and lengths of step k + depth - 1, read by the kernel when it issues
-        // that step's loads. A row needs the bytes [0, 32 tiles + phase + 11).
-        for (int k = 0; k + depth - 1 < K; ++k) {
-            uint8_t* rk = Rb + static_cast<size_t>(k) * RL.size;
-            const uint8_t* rn = Rb + static_cast<size_t>(k + depth - 1) * RL.size;
-            std::memcpy(rk + RL.next_rs, &rsv[bi * npad + cps * (k + depth - 1)], 4 * cps);
-            int32_t tiles;
-            std::memcpy(&tiles, rn + RL.tiles, 4);
-            const int32_t need = std::min(row / 16, (32 * tiles + 15 + 11 + 15) / 16);
-            std::memcpy(rk + RL.next_need, &need, 4);
-        }
+        DmBlock& b = blocks[bi];
+        const int rc = block_tables(p, b, b.cps, g, npad, &rsv[bi * npad], &rec[static_cast<size_t>(b.rec256) * 256],
+                                    nullptr, nullptr);
+        if (rc != AA_OK) return rc;
     }
     return AA_OK;
 }
@@ -197,11 +277,11 @@ int prepare_mfma(const aa_plan_s* p, const DedispVariant& V, DedispTables& t) {
     std::vector<DmBlock> blocks;
     std::vector<int32_t> rsv;
     std::vector<uint8_t> rec;
-    const int cps = mfma_cps(V.layout);
+    const int cps = mfma_cps(V.layout);   // 0: mixed by trial range
     const int rc0 = build_mfma_tables(p, V.tile, V.depth, V.max_tiles, cps, blocks, rsv, rec);
     if (rc0 != AA_OK) return rc0;
     t.bd = 32;
-    t.nchan_pad = (p->nchan + cps - 1) / cps * cps;
+    t.nchan_pad = cps == 4 ? (p->nchan + 3) / 4 * 4 : (p->nchan + 7) / 8 * 8;
     t.max_row = mfma_row_bytes(V.max_tiles);
     t.blocks = blocks;
     if (p->device >= 0) {
@@ -221,7 +301,7 @@ int prepare_variant(aa_plan_s* p, int v) {
     DedispTables& T = p->tables[v];
     if (T.variant == v) return AA_OK;
     const DedispVariant& V = kDedispVariants[v];
-    if (V.layout == 4 || V.layout == 5) {
+    if (V.layout >= 4) {
         DedispTables t;
         t.variant = v;
         const int rc = prepare_mfma(p, V, t);
@@ -253,7 +333,7 @@ int prepare_variant(aa_plan_s* p, int v) {
             omax = std::max(omax, m);
             ++count;
         }
-        DmBlock b{d, count, kTimeTile + 16 + (omax & ~15), 0, 0};
+        DmBlock b{d, count, kTimeTile + 16 + (omax & ~15), 0, 0, 0, 0};
         if (b.row > row_max) return fail(AA_EINVAL, "dedispersion tiling: a single trial does not fit the LDS row");
         max_row = std::max(max_row, b.row);
         blocks.push_back(b);

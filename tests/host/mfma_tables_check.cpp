@@ -1,8 +1,10 @@
-// Host check of the matrix-core dedispersion tables (layout 4): a scalar model of the
+// Host check of the matrix-core dedispersion tables (layouts 4-6): a scalar model of the
 // kernel's steps (staging with the same row starts, lengths and clamps, one-hot
 // residual selection, per-block flush at t' - e) over the tables that build_mfma_tables
 // produces, compared with D[d][t] = sum_c X[c][t + s[d][c]] computed directly.
-// Host-only plan: no GPU needed. Usage: mfma_tables_check TILE DEPTH [MAX_TILES [CPS]]
+// Host-only plan: no GPU needed. Usage: mfma_tables_check TILE DEPTH [MAX_TILES [CPS [SPLIT]]]
+// CPS 0 mixes the step shapes by trial range; SPLIT (a fraction of the trials, or -1 for
+// the cost estimate's choice) places the change of shape.
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -12,7 +14,8 @@
 
 using namespace aa;
 
-static int TILE = 1024, DEPTH = 3, MAXT = 63, CPS = 4;
+static int TILE = 1024, DEPTH = 3, MAXT = 63, CPS_ARG = 4;
+static double SPLIT = -1.0;
 static int run_case(int nchan, int nsamp, double ftop, double foff, double tsamp, std::vector<double> dms, unsigned seed,
                     int max_tiles_check = 1 << 30) {
     aa_plan_desc_t d{};
@@ -24,10 +27,36 @@ static int run_case(int nchan, int nsamp, double ftop, double foff, double tsamp
     if (aa_plan(&d, &p) != AA_OK) { printf("plan failed: %s\n", aa_last_error()); return 1; }
     std::vector<DmBlock> blocks; std::vector<int32_t> rsv; std::vector<uint8_t> rec;
     const int ROW = mfma_row_bytes(MAXT);
-    const MfmaRec RL = mfma_rec(CPS);
-    const int RES = 32 / CPS;                      // residual range
-    if (build_mfma_tables(p, TILE, DEPTH, MAXT, CPS, blocks, rsv, rec) != AA_OK) { printf("tables failed: %s\n", aa_last_error()); return 1; }
-    const int nchan4 = (nchan + CPS - 1) / CPS * CPS, K4 = nchan4 / CPS;
+    const int split = SPLIT < 0 ? -1 : (int)(SPLIT * dms.size());
+    if (build_mfma_tables(p, TILE, DEPTH, MAXT, CPS_ARG, blocks, rsv, rec, split) != AA_OK) { printf("tables failed: %s\n", aa_last_error()); return 1; }
+    const int npad = CPS_ARG == 4 ? (nchan + 3) / 4 * 4 : (nchan + 7) / 8 * 8;
+    // blocks cover the trials in order; a mixed table has its 8-channel blocks first
+    {
+        int next = 0, prev_cps = 8;
+        size_t rec_at = 0;
+        for (const DmBlock& b : blocks) {
+            if (b.first != next || b.count < 1 || b.count > 32) { printf("blocks do not tile the trials\n"); return 1; }
+            if (b.cps != 4 && b.cps != 8) { printf("bad block shape %d\n", b.cps); return 1; }
+            if (CPS_ARG != 0 && b.cps != CPS_ARG) { printf("block shape differs from the variant's\n"); return 1; }
+            if (CPS_ARG == 0 && b.cps > prev_cps) { printf("8-channel block after a 4-channel block\n"); return 1; }
+            if ((size_t)b.rec256 * 256 != rec_at) { printf("record offsets not packed\n"); return 1; }
+            rec_at += (size_t)(npad / b.cps) * mfma_rec(b.cps).size;
+            next += b.count;
+            prev_cps = b.cps;
+        }
+        if (next != (int)dms.size() || rec_at != rec.size() || rsv.size() != blocks.size() * npad) {
+            printf("table sizes\n");
+            return 1;
+        }
+        if (CPS_ARG == 0 && split >= 0)
+            for (const DmBlock& b : blocks)
+                if ((b.cps == 8) != (b.first < split) || (b.cps == 8 && b.first + b.count > split)) {
+                    printf("block shape does not follow the split\n");
+                    return 1;
+                }
+    }
+    int n8 = 0;
+    for (const DmBlock& b : blocks) n8 += b.cps == 8;
     const int64_t M = p->maxshift, n_out = nsamp - M;
     const int64_t pitch = (nsamp + 255) / 256 * 256;
     const int64_t n_in16 = (nsamp + 15) & ~15;
@@ -40,7 +69,11 @@ static int run_case(int nchan, int nsamp, double ftop, double foff, double tsamp
     int maxnr = 0; double sumcb = 0; int ncb = 0;
     int tiles_done = 0;
     for (size_t bi = 0; bi < blocks.size(); ++bi) {
-        const uint8_t* R = &rec[bi * K4 * RL.size];
+        const int CPS = blocks[bi].cps;
+        const MfmaRec RL = mfma_rec(CPS);
+        const int RES = 32 / CPS;                      // residual range
+        const int nchan4 = npad, K4 = nchan4 / CPS;
+        const uint8_t* R = &rec[(size_t)blocks[bi].rec256 * 256];
         for (int k = 0; k < K4; ++k) if (*(int32_t*)(R + k * RL.size + RL.left) == 1) ncb++;
         for (int64_t ti = 0; ti < ntile && tiles_done < max_tiles_check; ++ti, ++tiles_done) {
             const int64_t t0 = ti * TILE;
@@ -128,16 +161,17 @@ static int run_case(int nchan, int nsamp, double ftop, double foff, double tsamp
                 }
         }
     }
-    printf("nchan %d nsamp %d ndm %zu: blocks %zu, channel blocks %d, max nr %d, checked %ld, bad %ld\n", nchan, nsamp,
-           dms.size(), blocks.size(), ncb, maxnr, checked, bad);
+    printf("nchan %d nsamp %d ndm %zu: blocks %zu (%d of 8 channels per step), channel blocks %d, max nr %d, checked %ld, bad %ld\n",
+           nchan, nsamp, dms.size(), blocks.size(), n8, ncb, maxnr, checked, bad);
     aa_plan_destroy(p);
     return bad != 0;
 }
 int main(int argc, char** argv) {
     if (argc > 2) { TILE = atoi(argv[1]); DEPTH = atoi(argv[2]); }
     if (argc > 3) MAXT = atoi(argv[3]);
-    if (argc > 4) CPS = atoi(argv[4]);
-    printf("tile %d depth %d max tiles %d channels per step %d\n", TILE, DEPTH, MAXT, CPS);
+    if (argc > 4) CPS_ARG = atoi(argv[4]);
+    if (argc > 5) SPLIT = atof(argv[5]);
+    printf("tile %d depth %d max tiles %d channels per step %d split %g\n", TILE, DEPTH, MAXT, CPS_ARG, SPLIT);
     int rc = 0;
     rc |= run_case(1, 3000, 1400.0, 1.0, 64e-6, {0.0, 10.0, 100.0}, 1);
     rc |= run_case(7, 5003, 1500.0, 3.0, 64e-6, {0, 12.5, 25, 37.5, 50}, 2);

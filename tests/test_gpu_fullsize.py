@@ -87,7 +87,7 @@ def test_survey_dedisp_sampled(survey):
     _check_plane(sv, dd, rng)
     # every matrix-core variant (any of them can be the autotuner's pick), and the first
     # variant of each other layout
-    check = {v for v, info in enumerate(Plan.variants()) if info["layout"] in (4, 5)}
+    check = {v for v, info in enumerate(Plan.variants()) if info["layout"] in (4, 5, 6)}
     layouts = {}
     for v, info in enumerate(Plan.variants()):
         layouts.setdefault(info["layout"], v)

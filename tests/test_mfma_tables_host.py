@@ -2,7 +2,7 @@
 the kernel's steps runs over the tables of a host-only plan and must reproduce the
 brute-force sum D[d][t] = sum_c X[c][t + s[d][c]] exactly, for every time-tile, staging-depth
 and channels-per-step configuration of the matrix-core variants (4 channels x 8 residuals
-and 8 x 4 per step), on shapes that span padded
+and 8 x 4 per step, and the two mixed by trial range), on shapes that span padded
 channels, single-trial DM blocks, wide DM steps and 4096-channel blocks at the
 63- and 31-tile channel-block limits. The harness is compiled with hipcc as host code."""
 
@@ -31,9 +31,13 @@ def harness(tmp_path_factory):
     return exe
 
 
-@pytest.mark.parametrize("tile,depth,max_tiles,cps", [(1024, 3, 63, 4), (896, 5, 63, 4), (768, 7, 63, 4), (512, 3, 31, 4),
-                                                      (480, 4, 31, 4), (864, 3, 63, 8), (512, 3, 31, 8)])
-def test_mfma_tables_reproduce_brute_force(harness, tile, depth, max_tiles, cps):
-    r = subprocess.run([harness, str(tile), str(depth), str(max_tiles), str(cps)], capture_output=True, text=True,
-                       timeout=600)
+# cps 0 mixes the step shapes by trial range: split -1 takes the cost estimate's split,
+# the others force it at that fraction of the trials (0: all 4-channel, 1: all 8-channel)
+@pytest.mark.parametrize("tile,depth,max_tiles,cps,split", [
+    (1024, 3, 63, 4, -1), (896, 5, 63, 4, -1), (768, 7, 63, 4, -1), (512, 3, 31, 4, -1), (480, 4, 31, 4, -1),
+    (864, 3, 63, 8, -1), (512, 3, 31, 8, -1),
+    (864, 3, 63, 0, -1), (864, 3, 63, 0, 0.5), (864, 3, 63, 0, 0.0), (864, 3, 63, 0, 1.0)])
+def test_mfma_tables_reproduce_brute_force(harness, tile, depth, max_tiles, cps, split):
+    r = subprocess.run([harness, str(tile), str(depth), str(max_tiles), str(cps), str(split)], capture_output=True,
+                       text=True, timeout=600)
     assert r.returncode == 0 and "ALL OK" in r.stdout, r.stdout + r.stderr
