@@ -198,21 +198,26 @@ int block_tables(const aa_plan_s* p, DmBlock& blk, int cps, const MfmaGeom& g, i
     return AA_OK;
 }
 
-// Relative cost of a block's work per time tile on MI355X, fitted to the measured
-// survey launches of the two step shapes (254 and 255 ms): a flushed tile costs about
-// 4.2 tile-steps (the flush plus the per-run overhead).
-constexpr double kFlushPerTileStep = 4.2;
+// Estimated launch time (ns) of a block's work on MI355X, fitted to timings of the two
+// step shapes over trial ranges of the survey plan: a work-group step (its staging, wait
+// and barrier) costs 1.63 ns of launch time with 4 channels and 2.17 ns with 8, a
+// tile-step 0.018 ns and a flushed tile 0.16 ns.
+double block_cost_ns(int cps, int64_t ntile, int K, int64_t tile_steps, int64_t flush_tiles) {
+    const double step = cps == 8 ? 2.17 : 1.63;
+    return static_cast<double>(ntile) * (step * K + 0.018 * static_cast<double>(tile_steps) +
+                                         0.16 * static_cast<double>(flush_tiles));
+}
 
 }  // namespace
 
 int build_mfma_tables(const aa_plan_s* p, int tile, int depth, int max_tiles, int cps, std::vector<DmBlock>& blocks,
                       std::vector<int32_t>& rsv, std::vector<uint8_t>& rec, int split_at) {
-    const int nchan = p->nchan;
     if (cps != 4 && cps != 8 && cps != 0) return fail(AA_EINVAL, "matrix-core tiling: 4, 8 or mixed channels per step");
-    MfmaGeom g{tile, depth, max_tiles, max_tiles * 32 - tile, mfma_row_bytes(max_tiles)};
+    const MfmaGeom g{tile, depth, max_tiles, max_tiles * 32 - tile, mfma_row_bytes(max_tiles)};
     if (tile % 32 || tile < 256 || g.spread_max < 0 || depth < 3 || (max_tiles != 31 && max_tiles != 63))
         return fail(AA_EINVAL, "matrix-core tiling: bad tile, depth or channel-block span");
-    const int npad = (nchan + (cps == 4 ? 3 : 7)) / (cps == 4 ? 4 : 8) * (cps == 4 ? 4 : 8);
+    const int nchan = p->nchan;
+    const int npad = cps == 4 ? (nchan + 3) / 4 * 4 : (nchan + 7) / 8 * 8;
     std::vector<int32_t> fmin(nchan), fmax(nchan);
     // block shapes: the split trial below which blocks use 8 channels per step
     int split = cps == 8 ? p->ndm : 0;
@@ -220,17 +225,19 @@ int build_mfma_tables(const aa_plan_s* p, int tile, int depth, int max_tiles, in
         split = std::min(split_at, p->ndm);
     } else if (cps == 0) {
         // price each shape's own partition, then take the split (at an 8-channel block
-        // boundary) that minimises the estimated cost
+        // boundary) with the lowest estimated launch time
+        const int64_t n_out = std::max<int64_t>(p->nsamp - p->maxshift, 1);
         std::vector<int32_t> rsv_tmp(npad);
         std::vector<std::pair<int, double>> c8, c4;   // (first trial, cost)
         for (int shape : {8, 4}) {
+            const int64_t ntile = (n_out + g.tile - 1) / g.tile;
             std::vector<uint8_t> rec_tmp(static_cast<size_t>(npad / shape) * mfma_rec(shape).size);
             for (int d0 = 0; d0 < p->ndm;) {
                 DmBlock b{d0, grow_block(p, d0, shape, g, fmin, fmax), 0, 0, 0, shape, 0};
                 int64_t mt = 0, ft = 0;
                 const int rc = block_tables(p, b, shape, g, npad, rsv_tmp.data(), rec_tmp.data(), &mt, &ft);
                 if (rc != AA_OK) return rc;
-                (shape == 8 ? c8 : c4).push_back({d0, static_cast<double>(mt) + kFlushPerTileStep * static_cast<double>(ft)});
+                (shape == 8 ? c8 : c4).push_back({d0, block_cost_ns(shape, ntile, npad / shape, mt, ft)});
                 d0 += b.count;
             }
         }
@@ -265,8 +272,8 @@ int build_mfma_tables(const aa_plan_s* p, int tile, int depth, int max_tiles, in
     rec.assign(rec_bytes, 0);
     for (size_t bi = 0; bi < nblk; ++bi) {
         DmBlock& b = blocks[bi];
-        const int rc = block_tables(p, b, b.cps, g, npad, &rsv[bi * npad], &rec[static_cast<size_t>(b.rec256) * 256],
-                                    nullptr, nullptr);
+        const int rc = block_tables(p, b, b.cps, g, npad, &rsv[bi * npad],
+                                    &rec[static_cast<size_t>(b.rec256) * 256], nullptr, nullptr);
         if (rc != AA_OK) return rc;
     }
     return AA_OK;
