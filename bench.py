@@ -42,6 +42,7 @@ I8_MFMA_PEAK_TOPS = 5000.0
 TRAFFIC_BYTES = {
     ("survey_4096ch_1M", 12): 175.5e9 + 12.15e9,
     ("survey_4096ch_1M", 17): 279.1e9 + 12.15e9,
+    ("survey_4096ch_1M", 20): 202.0e9 + 12.15e9,
 }
 
 
