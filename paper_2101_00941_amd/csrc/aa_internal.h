@@ -43,11 +43,11 @@ struct DedispVariant {
                      // 6: layouts 5 and 4 mixed by trial range (per DM block)
     int tile;        // output samples per work-group (time tile)
     int depth;       // staging buffers in the LDS ring (loads run depth - 1 steps ahead)
-    int max_tiles;   // layout 4: a channel block spans at most 32 * max_tiles rows of t' (31 or 63)
+    int max_tiles;   // layouts 4-6: a channel block spans at most 32 * max_tiles rows of t' (31 or 63)
 };
 constexpr int kNumDedispVariants = 21;
 
-// Matrix-core variant (layout 4). Within a block of up to 32 trials (first trial d0)
+// Matrix-core variants (layouts 4-6). Within a block of up to 32 trials (first trial d0)
 // and a run of channels, the shift splits exactly as
 //   s[d][c] = base[c] + E[d] + r[d][c],  base[c] = s[d0][c],  0 <= r < 8.
 // For rows t' of a shifted time axis, the partial sum over the run,
@@ -113,7 +113,7 @@ struct DedispTables {
     DmBlock* d_blocks = nullptr;
     int32_t* d_base = nullptr;
     int32_t* d_offs = nullptr;
-    uint8_t* d_pad = nullptr;        // layout 4: one staged row of 0x80 bytes (padded channels)
+    uint8_t* d_pad = nullptr;        // layouts 4-6: one staged row of 0x80 bytes (padded channels)
 };
 
 // Arguments of one dedispersion launch (one beam), passed by value or from a device table.

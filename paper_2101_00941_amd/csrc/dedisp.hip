@@ -330,7 +330,7 @@ __device__ __forceinline__ void wait_vmcnt(int n) {
     }
 }
 
-// Matrix-core dedispersion of one (DM block, time tile), layouts 4 and 5. The shift
+// Matrix-core dedispersion of one (DM block, time tile), layouts 4-6. The shift
 // of a trial d of the block at channel c is s = base[c] + E[d] + r[d][c], with
 // 0 <= r < R inside a channel block (the tables are built on the host, tiling.cpp). So
 //   D[d][t] = sum over channel blocks of P[t + e[d]][d],
@@ -339,7 +339,7 @@ __device__ __forceinline__ void wait_vmcnt(int n) {
 // the data matrix A[t'][(c, r)] (a sliding R-byte window per channel) and the one-hot
 // matrix B[(c, r)][d], computed exactly by v_mfma_i32_32x32x32_i8: rows are 32 values
 // of t', columns the 32 trials, and one step contracts CPS channels x R residuals,
-// CPS x R = 32 (4 x 8 for layout 4, 8 x 4 for layout 5).
+// CPS x R = 32 (4 x 8 for layout 4, 8 x 4 for layout 5, the block's own shape for 6).
 // Input bytes enter as x - 128 (signed 8-bit), and 128 * nchan is added back at the end.
 //  * W = 8 or 16 waves. Wave w owns the tiles w + W j of 32 rows of t' (a channel block
 //    needs TILE / 32 to MAXT tiles, MAXT = 63 or 31, so a wave owns NT = TILE / (32 W)
