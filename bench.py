@@ -136,6 +136,8 @@ def streamed(a):
     probe = h2d_probe(torch, nchan, chunk, nsamp)
     log(f"[bench] H2D probe {probe}")
     plan = Plan.from_workload(w)
+    if a.variant != "auto":
+        plan.set_variant(int(a.variant))
     ndm = plan.info["ndm"]
     budget = int(a.budget_gb * (1 << 30))
     rows = []
@@ -182,7 +184,8 @@ def streamed(a):
     plain = next(r["wall_ms"] for r in rows if r["mode"] == "plain")
     for r in rows:
         r["speedup_vs_plain"] = plain / r["wall_ms"]
-    return dict(workload=w["name"], chunk=chunk, ndm=ndm, nchan=nchan, nsamp=nsamp, h2d_probe=probe,
+    return dict(workload=w["name"], chunk=chunk, ndm=ndm, nchan=nchan, nsamp=nsamp, dedisp_variant=plan.variant,
+                h2d_probe=probe,
                 hw_queues=os.environ.get("GPU_MAX_HW_QUEUES", "default"), runs=rows)
 
 
@@ -210,6 +213,9 @@ def serving(a):
         pool.append(h)
     plans = [Plan(nchan, 1 << 20, b["f_top"], b["foff"], b["tsamp"], b["dms"], b["widths"], b["threshold"],
                   b["stat_block"]) for b in beams]
+    if a.variant != "auto":
+        for p in plans:
+            p.set_variant(int(a.variant))
     out = {}
     for scale in a.rate_scale:
         arrivals = poisson_arrivals(beams, a.serve_seconds, rate_scale=scale)
@@ -253,7 +259,7 @@ def serving(a):
             log(f"[bench] serving x{scale:g} {mode}: {len(arrivals)} chunks, p50 {res['p50_ms']:.1f} ms, "
                 f"p99 {res['p99_ms']:.1f} ms, {res['dm_trial_samples_per_s']:.3e} DM-trial*samples/s, "
                 f"arena peak {res['arena_peak_gb']:.1f} GB")
-    return dict(workload="serving_32beams", chunk=chunk, nchan=nchan, beams=len(beams),
+    return dict(workload="serving_32beams", chunk=chunk, nchan=nchan, beams=len(beams), dedisp_variant=plans[0].variant,
                 seconds=a.serve_seconds, streams=a.serve_streams, hbm_budget_gb=a.budget_gb, results=out)
 
 
@@ -324,7 +330,9 @@ def main():
     ap.add_argument("--workload", default="survey_4096ch_1M")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cap", type=int, default=1 << 20)
-    ap.add_argument("--variant", default="auto", help="dedispersion kernel variant, or 'auto' (autotuner)")
+    ap.add_argument("--variant", default="auto",
+                    help="dedispersion kernel variant, or 'auto' (resident and batched modes: the autotuner; "
+                         "streamed and serving modes: the plan default)")
     ap.add_argument("--ndm", type=int, default=0, help="use only the first NDM trials (profiling runs)")
     ap.add_argument("--mode", default="resident", choices=["resident", "streamed", "serving", "batched"])
     ap.add_argument("--beams", type=int, default=32)
