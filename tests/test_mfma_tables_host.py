@@ -7,6 +7,7 @@ channels, single-trial DM blocks, wide DM steps and 4096-channel blocks at the
 63- and 31-tile channel-block limits. The harness is compiled with hipcc as host code."""
 
 import os
+import re
 import shutil
 import subprocess
 
@@ -41,3 +42,8 @@ def test_mfma_tables_reproduce_brute_force(harness, tile, depth, max_tiles, cps,
     r = subprocess.run([harness, str(tile), str(depth), str(max_tiles), str(cps), str(split)], capture_output=True,
                        text=True, timeout=600)
     assert r.returncode == 0 and "ALL OK" in r.stdout, r.stdout + r.stderr
+    if cps == 0 and (split < 0 or 0 < split < 1):
+        # the mixed tables must really mix: some case holds blocks of both shapes
+        mixed = [(int(m.group(1)), int(m.group(2)))
+                 for m in re.finditer(r"blocks (\d+) \((\d+) of 8 channels per step\)", r.stdout)]
+        assert any(0 < n8 < n for n, n8 in mixed), r.stdout
