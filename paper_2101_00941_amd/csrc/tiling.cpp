@@ -112,8 +112,9 @@ int grow_block(const aa_plan_s* p, int d0, int cps, const MfmaGeom& g, std::vect
     return count;
 }
 
-// Row starts (npad entries) and records (npad / cps of them) of one block; `work` gets the
-// block's tile-steps (one matrix op per 32-row tile and step) and flushed tiles per time tile.
+// Row starts (npad entries) and records (npad / cps of them) of one block. When not null,
+// mfma_tiles and flush_tiles receive the block's tile-steps (one matrix op per 32-row tile
+// and step) and flushed tiles, per time tile.
 int block_tables(const aa_plan_s* p, DmBlock& blk, int cps, const MfmaGeom& g, int npad, int32_t* rsv, uint8_t* Rb,
                  int64_t* mfma_tiles, int64_t* flush_tiles) {
     const int nchan = p->nchan, R = 32 / cps, K = npad / cps;
