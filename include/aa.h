@@ -217,12 +217,16 @@ typedef struct {
     int64_t        n_in;       /* samples per channel */
 } aa_batch_beam_t;
 
+#define AA_MAX_VARIANTS 32   /* upper bound of aa_variant_count() */
+
 typedef struct {
     int32_t groups;            /* persistent launches used */
     int32_t variant;           /* dedispersion variant used */
     int64_t items;             /* (beam, DM block, time tile) items over all groups */
     float   ms_dedisp;         /* HIP-event time of the dedispersion launches */
     float   ms_search;         /* HIP-event time of the single-pulse searches */
+    int32_t tuned_beam;        /* beam the autotuner timed (variant -1), else -1 */
+    float   tune_ms[AA_MAX_VARIANTS];  /* its per-variant mean ms (-1: not timed or from cache) */
 } aa_batch_info_t;
 
 int aa_batch_run(const aa_batch_beam_t* beams, int32_t nbeams, int32_t variant, void* d_work, size_t work_bytes,
@@ -267,6 +271,16 @@ int aa_batch_run(const aa_batch_beam_t* beams, int32_t nbeams, int32_t variant, 
  * plain single-stream baseline). AA_PIPE_TIMING records HIP-event times for copies
  * and kernels; aa_pipeline_stats reports them. AA_PIPE_STAGED: staged pageable
  * input, as above (section 2's pinned bounce buffers and per-stream host threads).
+ * Errors inside the scheduler: a copy, wait, launch or event call that fails for a
+ * chunk does not stop the pipeline. The chunk completes with status AA_EHIP, aa_poll
+ * sets the calling thread's aa_last_error() to the failure's message, and the chunk's
+ * arena block and result slot are released once its stream has passed them. Other
+ * chunks and beams are not affected.
+ * Environment, read at create:
+ *   AA_LOG=path     appends one JSON line per finished chunk (tag, beam, starts, sub-chunks,
+ *                   candidates, status, queue and total latency in seconds).
+ *   AA_FAULT=unit:N test hook: the N-th sub-chunk issued (counting from 0) is not launched
+ *                   and its chunk completes with AA_EHIP, as if its launch had failed.
  */
 #define AA_PIPE_SERIAL 1u
 #define AA_PIPE_TIMING 2u
@@ -284,6 +298,9 @@ typedef struct {
     int32_t  result_slots;  /* sub-chunks in flight at once (0 means 4 * nstreams)            */
     int64_t  hbm_budget;    /* arena bytes (0: size for one chunk per stream + all histories) */
     uint32_t flags;         /* AA_PIPE_SERIAL | AA_PIPE_TIMING | AA_PIPE_SDMA_COPY | AA_PIPE_STAGED */
+    int64_t  min_piece_work;/* smallest sub-chunk in DM-trial x channel x start units: a chunk is
+                               split into min(nstreams, work / min_piece_work) sub-chunks, at least
+                               one. 0 means 2^33; < 0 always splits into nstreams sub-chunks    */
 } aa_pipeline_opts_t;
 
 typedef struct {
@@ -310,6 +327,15 @@ int aa_pipeline_create(const aa_pipeline_opts_t* opts, aa_pipeline_t* out);
 /* Registers a beam with its plan (created on the pipeline's device). Plan-time call:
  * allocates the beam's history from the arena. Returns the beam id in *beam. */
 int aa_pipeline_add_beam(aa_pipeline_t pipe, aa_plan_t plan, int32_t* beam);
+/* Resume (checkpoint/restart; the paper has no such passage, this serves restarting a
+ * stream after a pipeline was torn down). Registers a beam whose search continues at the
+ * absolute start t_resume, a multiple of the plan's stat_block: the t_end of the beam's
+ * last result is such a checkpoint. The beam's first submitted sample must be the
+ * absolute sample h = (t_resume - 1) rounded down to a multiple of 16 (0 if t_resume is
+ * 0), so the submits re-send the samples [h, ...) that the old beam's device tail held.
+ * Candidates then carry absolute starts and equal those of an uninterrupted run.
+ * Errors: AA_EINVAL for a t_resume that is negative or not block-aligned. */
+int aa_pipeline_add_beam_at(aa_pipeline_t pipe, aa_plan_t plan, int64_t t_resume, int32_t* beam);
 int aa_stream_submit(aa_pipeline_t pipe, int32_t beam, const uint8_t* h_chunk, int64_t nsamp, int64_t pitch,
                      uint64_t tag, uint32_t flags);
 /* Waits up to timeout_us (0: no wait, <0: forever) for a finished chunk. AA_EAGAIN if none. */

@@ -45,7 +45,7 @@ class VariantInfo(C.Structure):
 class PipelineOpts(C.Structure):
     _fields_ = [("nstreams", C.c_int32), ("max_beams", C.c_int32), ("max_chunk", C.c_int64),
                 ("cand_cap", C.c_int32), ("result_slots", C.c_int32), ("hbm_budget", C.c_int64),
-                ("flags", C.c_uint32)]
+                ("flags", C.c_uint32), ("min_piece_work", C.c_int64)]
 
 
 class Result(C.Structure):
@@ -72,7 +72,7 @@ class BatchBeam(C.Structure):
 
 class BatchInfo(C.Structure):
     _fields_ = [("groups", C.c_int32), ("variant", C.c_int32), ("items", C.c_int64), ("ms_dedisp", C.c_float),
-                ("ms_search", C.c_float)]
+                ("ms_search", C.c_float), ("tuned_beam", C.c_int32), ("tune_ms", C.c_float * 32)]
 
 
 class AAError(RuntimeError):
@@ -113,6 +113,7 @@ def lib():
         "aa_autotune": (C.c_int, [vp, vp, i64, i64, vp, i64, i32, vp, C.POINTER(C.c_float)]),
         "aa_pipeline_create": (C.c_int, [C.POINTER(PipelineOpts), C.POINTER(vp)]),
         "aa_pipeline_add_beam": (C.c_int, [vp, vp, C.POINTER(i32)]),
+        "aa_pipeline_add_beam_at": (C.c_int, [vp, vp, i64, C.POINTER(i32)]),
         "aa_stream_submit": (C.c_int, [vp, i32, vp, i64, i64, C.c_uint64, C.c_uint32]),
         "aa_poll": (C.c_int, [vp, C.POINTER(Result), i32]),
         "aa_release": (C.c_int, [vp, C.c_uint64]),

@@ -204,10 +204,11 @@ class Pipeline:
     """
 
     def __init__(self, nstreams=4, max_beams=1, max_chunk=1 << 18, cand_cap=1 << 14, result_slots=0,
-                 hbm_budget=8 << 30, serial=False, timing=False, sdma_copy=False, staged=False):
+                 hbm_budget=8 << 30, serial=False, timing=False, sdma_copy=False, staged=False, min_piece_work=0):
         o = N.PipelineOpts()
         o.nstreams, o.max_beams, o.max_chunk = int(nstreams), int(max_beams), int(max_chunk)
         o.cand_cap, o.result_slots, o.hbm_budget = int(cand_cap), int(result_slots), int(hbm_budget)
+        o.min_piece_work = int(min_piece_work)
         o.flags = ((N.AA_PIPE_SERIAL if serial else 0) | (N.AA_PIPE_TIMING if timing else 0)
                    | (N.AA_PIPE_SDMA_COPY if sdma_copy else 0) | (N.AA_PIPE_STAGED if staged else 0))
         h = C.c_void_p()
@@ -216,9 +217,13 @@ class Pipeline:
         self._keep = {}
         self.plans = []
 
-    def add_beam(self, plan):
+    def add_beam(self, plan, t_resume=None):
+        """aa_pipeline_add_beam, or aa_pipeline_add_beam_at when t_resume is given."""
         b = C.c_int32()
-        N.check(N.lib().aa_pipeline_add_beam(self._h, plan.handle, C.byref(b)))
+        if t_resume is None:
+            N.check(N.lib().aa_pipeline_add_beam(self._h, plan.handle, C.byref(b)))
+        else:
+            N.check(N.lib().aa_pipeline_add_beam_at(self._h, plan.handle, int(t_resume), C.byref(b)))
         self.plans.append(plan)
         return b.value
 
@@ -298,4 +303,6 @@ def batch_run(beams, variant=-1, work=None, work_bytes=None, cap=1 << 16, static
     for i in range(n):
         k = int(min(counts[i], cap))
         out.append(raw[i * cap * 24:(i * cap + k) * 24].view(N.CANDIDATE_DTYPE).copy())
-    return out, counts, {k: getattr(info, k) for k, _ in N.BatchInfo._fields_}
+    d = {k: getattr(info, k) for k, _ in N.BatchInfo._fields_}
+    d["tune_ms"] = [float(v) for v in info.tune_ms][:N.lib().aa_variant_count()]
+    return out, counts, d

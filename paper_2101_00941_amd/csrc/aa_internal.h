@@ -46,6 +46,7 @@ struct DedispVariant {
     int max_tiles;   // layouts 4-6: a channel block spans at most 32 * max_tiles rows of t' (31 or 63)
 };
 constexpr int kNumDedispVariants = 21;
+static_assert(kNumDedispVariants <= AA_MAX_VARIANTS, "aa_batch_info_t::tune_ms holds every variant");
 
 // Matrix-core variants (layouts 4-6). Within a block of up to 32 trials (first trial d0)
 // and a run of channels, the shift splits exactly as

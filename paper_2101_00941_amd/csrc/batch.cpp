@@ -61,12 +61,16 @@ extern "C" int aa_batch_run(const aa_batch_beam_t* beams, int32_t nbeams, int32_
             return fail(AA_ENOMEM, "aa_batch_run: one beam's plane does not fit the work buffer");
 
     // variant: given, or tuned on the beam with the most work
+    float tune_ms[AA_MAX_VARIANTS];
+    for (float& m : tune_ms) m = -1.0f;
+    int tuned_beam = -1;
     if (variant < 0) {
         const aa_batch_beam_t& b = beams[biggest];
         int32_t* plane = reinterpret_cast<int32_t*>(static_cast<uint8_t*>(d_work) + header);
-        const int rc = aa_autotune(b.plan, b.d_in, b.in_pitch, b.n_in, plane, bp[biggest].opitch, 1, stream_, nullptr);
+        const int rc = aa_autotune(b.plan, b.d_in, b.in_pitch, b.n_in, plane, bp[biggest].opitch, 1, stream_, tune_ms);
         if (rc != AA_OK) return rc;
         variant = b.plan->variant;
+        tuned_beam = biggest;
     }
     if (variant >= kNumDedispVariants) return fail(AA_EINVAL, "aa_batch_run: unknown variant");
     for (int i = 0; i < nbeams; ++i) {
@@ -155,6 +159,8 @@ extern "C" int aa_batch_run(const aa_batch_beam_t* beams, int32_t nbeams, int32_
         info->items = items_all;
         info->ms_dedisp = ms_d;
         info->ms_search = ms_s;
+        info->tuned_beam = tuned_beam;
+        for (int v = 0; v < AA_MAX_VARIANTS; ++v) info->tune_ms[v] = tune_ms[v];
     }
     return rc;
 }

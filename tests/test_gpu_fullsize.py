@@ -8,11 +8,11 @@ oracle checks sampled outputs, each computed on its own:
     samples and at a random one, and full 32768-sample runs of a few trials, for
     the autotuned variant, every matrix-core variant and one variant of each other
     kernel family;
-  * candidates: regions of one trial x one statistics block, where the oracle
-    dedisperses the trial and its two neighbours over the block (plus boxcar and
-    peak halo) and runs its own search. Regions are those of the strongest GPU
-    candidates and a few random ones. The GPU list restricted to the region must
-    equal the oracle's exactly.
+  * candidates: every 100th trial and the two trials on each side of every
+    injected pulse's DM (127 rows, chosen from the signal model), over the full
+    time range. The oracle dedisperses each of those rows and its neighbours over
+    all samples (220 rows, threaded over the host cores) and runs its own search.
+    The GPU list restricted to those rows must equal the oracle's exactly.
 """
 
 import numpy as np
@@ -101,36 +101,78 @@ def test_survey_dedisp_sampled(survey):
     plan.set_variant(chosen)
 
 
-def test_survey_candidates_regions(survey):
+def _checked_rows(w, ndm):
+    """Every 100th trial, and the two trials on each side of the trial nearest to each
+    injected pulse's DM (the rows come from the signal model, not from the GPU list)."""
+    dms = np.asarray(w["dms"])
+    rows = set(range(0, ndm, 100))
+    for p in w["pulses"]:
+        r = int(np.argmin(np.abs(dms - p.dm)))
+        rows |= {q for q in range(r - 2, r + 3) if 0 <= q < ndm}
+    return sorted(rows)
+
+
+def _runs(rows):
+    """Contiguous runs [a, b] of a sorted row list."""
+    out = []
+    for r in rows:
+        if out and r == out[-1][1] + 1:
+            out[-1][1] = r
+        else:
+            out.append([r, r])
+    return out
+
+
+def test_survey_candidates_full_time(survey):
+    """GPU candidates over the full time range of the checked rows equal the oracle's,
+    which dedisperses each checked row and its two neighbours over all 1,012,255
+    samples and runs its own search (statistics, boxcars, peaks) over all starts."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+
     import torch
+    from paper_2101_00941_amd import candidates_as_tuples, candidates_to_numpy
     sv = survey
     w, plan, x, dd, info, s = sv["w"], sv["plan"], sv["x"], sv["dd"], sv["info"], sv["s"]
     n_in, ndm, T, B = w["nsamp"], info["ndm"], info["n_start"], info["stat_block"]
-    M, wmax = int(s.max()), max(w["widths"])
+    M = int(s.max())
     plan.dedisperse(x, n_in=n_in, out=dd)
     cap = 1 << 20
     work = torch.empty(plan.work_bytes(T), dtype=torch.uint8, device="cuda")
     cand, count, _ = plan.single_pulse(dd, work=work, cap=cap)
     torch.cuda.synchronize()
-    from paper_2101_00941_amd import candidates_as_tuples, candidates_to_numpy
     got = candidates_as_tuples(candidates_to_numpy(cand, count))
-    say(f"  {len(got)} GPU candidates")
+    say(f"  {len(got)} GPU candidates (variant {plan.variant})")
     assert 0 < len(got) < cap
-    rng = np.random.default_rng(12)
-    top = sorted(got, key=lambda c: -c[3])[:10]
-    regions = {(c[0], c[1] // B) for c in top}
-    regions |= {(int(rng.integers(0, ndm)), int(rng.integers(0, (T + B - 1) // B))) for _ in range(3)}
-    regions |= {(0, 0), (ndm - 1, (T - 1) // B)}
+    rows = _checked_rows(w, ndm)
+    need = sorted({q for r in rows for q in (r - 1, r, r + 1) if 0 <= q < ndm})
+    say(f"  oracle: {len(rows)} checked rows, {len(need)} dedispersed rows over the full time range")
     x_np = sv["x_np"]
-    for r, blk in sorted(regions):
-        b0, b1 = blk * B, min(blk * B + B, T)
-        lo = max(b0 - 1, 0)
-        hi_start = b1 + 1 if b1 + 1 <= T else T               # starts the peak test can touch
-        cols = hi_start + wmax - 1 - lo                          # plane columns those starts need
-        rows = [q for q in (r - 1, r, r + 1) if 0 <= q < ndm]
-        Dr = oracle.dedisperse_rows(x_np[:, lo:lo + cols + M], s, rows, maxshift=M)
-        want, _ = oracle.single_pulse(Dr, lo, b0, b1, T, w["widths"], w["threshold"], B, row0=rows[0], ndm=ndm,
-                                      report_rows=[r])
-        have = [c for c in got if c[0] == r and b0 <= c[1] < b1]
-        say(f"  region trial {r} starts [{b0}, {b1}): {len(want)} candidates")
-        assert_candidates_equal(have, want)
+
+    def one_row(q):
+        return q, oracle.dedisperse_rows(x_np, s, [q], n_in, M)[0]
+
+    Drow = {}
+    with ThreadPoolExecutor(max(1, min(16, os.cpu_count() or 1))) as pool:
+        for q, r in pool.map(one_row, need):
+            Drow[q] = r
+    want = []
+    for a, b in _runs(rows):
+        lo, hi = max(a - 1, 0), min(b + 1, ndm - 1)
+        D = np.stack([Drow[q] for q in range(lo, hi + 1)])
+        c, _ = oracle.single_pulse(D, 0, 0, T, T, w["widths"], w["threshold"], B, row0=lo, ndm=ndm,
+                                   report_rows=list(range(a, b + 1)))
+        want.extend(c)
+    want.sort(key=lambda c: (c[0], c[1]))
+    rowset = set(rows)
+    have = [c for c in got if c[0] in rowset]
+    say(f"  {len(want)} oracle candidates on the checked rows, {len(have)} GPU")
+    assert_candidates_equal(have, want)
+    # the injected pulses are found at their DM (within two trials) and arrival time
+    dms = np.asarray(w["dms"])
+    found = 0
+    for p in w["pulses"]:
+        r = int(np.argmin(np.abs(dms - p.dm)))
+        found += any(abs(c[0] - r) <= 2 and abs(c[1] - p.t0) <= 512 for c in want)
+    say(f"  {found} of {len(w['pulses'])} injected pulses found")
+    assert found >= len(w["pulses"]) - 2
