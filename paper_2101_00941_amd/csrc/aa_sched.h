@@ -111,6 +111,18 @@ inline std::vector<Piece> split_blocks(int64_t e, int64_t e2, int64_t block, int
     return out;
 }
 
+// Number of sub-chunks for a range of `work` DM-trial x channel x start units. The
+// range is split over at most `nstreams` compute streams, but no piece gets less than
+// `min_work` units: splitting a small chunk only adds launches, events and copies per
+// piece, and the streams still overlap consecutive chunks. min_work <= 0 always splits
+// into nstreams pieces.
+inline int sub_chunks(int64_t work, int64_t min_work, int nstreams) {
+    if (nstreams < 1) return 1;
+    if (min_work <= 0) return nstreams;
+    const int64_t k = work / min_work;
+    return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(nstreams, k)));
+}
+
 // Input window [w0, w1) of a piece, with w0 rounded down to a 16-byte column of the
 // beam history (whose column 0 holds absolute sample h0).
 inline void piece_window(const Piece& pc, int64_t h0, int64_t R2, int64_t maxshift, int64_t wmax, int64_t* w0,

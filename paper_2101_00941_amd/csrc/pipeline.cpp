@@ -22,6 +22,8 @@
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <functional>
@@ -65,6 +67,7 @@ struct Request {
     double t_submit = 0, t_admit = 0, t_done = 0;
     int64_t t_begin = 0, t_end = 0;
     int status = AA_OK;
+    std::string err;                // message of the first failure, handed to the aa_poll caller
     int64_t n_true = 0;
     std::vector<aa_candidate_t> cand;
     std::vector<Unit> units;
@@ -189,6 +192,13 @@ struct aa_pipeline_s {
     size_t bounce_bytes = 0;
     unsigned bounce_next = 0;
     StagePool stagers;
+    bool staging_active = false;         // the scheduler is filling a bounce buffer, lock released
+    std::condition_variable cv_stage;
+    // sub-chunk split, fault hook (AA_FAULT) and per-chunk log (AA_LOG)
+    int64_t min_piece_work = int64_t{1} << 33;
+    int64_t fault_unit = -1, units_issued = 0;
+    FILE* log = nullptr;
+    void log_result(const Request* r);
     bool staged() const { return opt.flags & AA_PIPE_STAGED; }
     int grow_bounce(size_t bytes);
 
@@ -210,12 +220,12 @@ struct aa_pipeline_s {
     bool serial() const { return opt.flags & AA_PIPE_SERIAL; }
 
     // ---- issue one request (lock held); returns false if resources are short ----
-    bool try_issue(Request* r);
+    bool try_issue(Request* r, std::unique_lock<std::mutex>& lk);
     void complete_units();
     void run();
 };
 
-bool aa_pipeline_s::try_issue(Request* r) {
+bool aa_pipeline_s::try_issue(Request* r, std::unique_lock<std::mutex>& lk) {
     Beam& bm = beams[r->beam];
     const aa_plan_s* p = bm.plan;
     const int64_t M = p->maxshift, W = p->wmax, B = p->stat_block;
@@ -223,11 +233,13 @@ bool aa_pipeline_s::try_issue(Request* r) {
     const int64_t R2 = bm.R + r->n;
     const ChunkRange cr = chunk_range(bm.e, R2, M, W, B, last);
     const int64_t e2 = cr.e2, t_total = cr.t_total;
-    const std::vector<Piece> pieces = split_blocks(bm.e, e2, B, opt.nstreams);
+    const int64_t work = static_cast<int64_t>(p->ndm) * p->nchan * (e2 - bm.e);
+    const std::vector<Piece> pieces = split_blocks(bm.e, e2, B, sub_chunks(work, min_piece_work, opt.nstreams));
     // keep the history from the left-halo column of the next start, rounded down to 16 bytes
     const int64_t h0n = bm.e > 0 ? ((bm.e - 1) & ~int64_t{15}) : 0;
     if (R2 - h0n > bm.cols) {
         r->status = fail(AA_EINVAL, "aa_stream_submit: chunk does not fit the beam history");
+        r->err = aa_last_error();
         return true;  // completes with an error below
     }
     // resources: one arena block and one pinned slot per piece
@@ -249,46 +261,73 @@ bool aa_pipeline_s::try_issue(Request* r) {
         for (size_t j = 0; j < got; ++j) arena.release(offs[j], need[j]);
         return false;
     }
+    const int64_t nchan = p->nchan;
+    // copy pieces (each with an event, so that a sub-chunk waits only for its window); the
+    // staged path keeps nstreams pieces, the size its bounce buffers were made for
+    const int npc = std::max<int>(1, std::min<int>(staged() ? opt.nstreams : static_cast<int>(std::max<size_t>(pieces.size(), 1)),
+                                                   static_cast<int>((r->n + 4095) / 4096)));
+    if (staged() && r->n > 0) {
+        // the widest piece the loop below can cut, against the bounce size set at add_beam
+        const int64_t widest = (r->n + npc - 1) / npc + 15 * (npc - 1);
+        if (static_cast<size_t>((widest + 15) & ~int64_t{15}) * static_cast<size_t>(nchan) > bounce_bytes) {
+            r->status = fail(AA_EINVAL, "aa_stream_submit: staged piece exceeds the bounce buffers");
+            r->err = aa_last_error();
+            for (size_t j = 0; j < pieces.size(); ++j) arena.release(offs[j], need[j]);
+            return true;
+        }
+    }
+    // Every enqueue below is checked. The first failure becomes the chunk's status; the
+    // remaining steps are still enqueued where they are safe, so that every sub-chunk ends
+    // with a recorded completion event (or a synchronised stream) before its memory is reused.
+    auto ok = [&](hipError_t e, const char* what) {
+        if (e == hipSuccess) return true;
+        (void)hipGetLastError();
+        if (r->status == AA_OK || r->status == AA_EOVERFLOW) {
+            r->status = hip_fail(e, what);
+            r->err = aa_last_error();
+        }
+        return false;
+    };
 
     // ---- copies (copy stream) ----
     const int nb = bm.cur < 0 ? 0 : (bm.cur + 1) % 2;
     hipStream_t cs = copy;
+    bool copies_ok = true;
     if (Request* prev = bm.last_user[nb]) {
         for (Unit& u : prev->units)
-            if (!u.complete && u.done && !serial()) (void)hipStreamWaitEvent(cs, u.done, 0);
+            if (!u.complete && u.done && !serial())
+                copies_ok &= ok(hipStreamWaitEvent(cs, u.done, 0), "pipeline: copy stream wait");
     }
     if (timing()) {
         r->c0 = get_event(true);
-        (void)hipEventRecord(r->c0, cs);
+        if (!r->c0 || !ok(hipEventRecord(r->c0, cs), "pipeline: event record")) {
+            put_event(r->c0, true);
+            r->c0 = nullptr;
+        }
     }
-    const int64_t nchan = p->nchan;
+    if (!copies_ok) {
+        // the history buffer may still be read by the previous chunk: writing it now would race
+        (void)hipStreamSynchronize(cs);
+        for (Unit& u : bm.last_user[nb]->units)
+            if (!u.complete) (void)hipStreamSynchronize(u.stream < 0 ? cs : comp[u.stream]);
+    }
     if (bm.cur >= 0 && bm.R > h0n) {
-        (void)hipMemcpy2DAsync(bm.buf[nb], bm.pitch, bm.buf[bm.cur] + (h0n - bm.h0), bm.pitch, bm.R - h0n, nchan,
-                               hipMemcpyDeviceToDevice, cs);
+        ok(hipMemcpy2DAsync(bm.buf[nb], bm.pitch, bm.buf[bm.cur] + (h0n - bm.h0), bm.pitch, bm.R - h0n, nchan,
+                            hipMemcpyDeviceToDevice, cs),
+           "pipeline: device tail copy");
     }
     // H2D of the new samples in pieces, with an event after each. Mapped pinned rows are
     // gathered by a kernel when every row start is 16-byte aligned; otherwise the
     // runtime's 2-D copy is used.
     const uint8_t* hdev = nullptr;
     int64_t col = bm.R - h0n, src = 0;
-    if (!(opt.flags & AA_PIPE_SDMA_COPY) && r->n > 0 && (reinterpret_cast<uintptr_t>(r->h) & 15) == 0 &&
+    if (!(opt.flags & AA_PIPE_SDMA_COPY) && !staged() && r->n > 0 && (reinterpret_cast<uintptr_t>(r->h) & 15) == 0 &&
         (r->pitch & 15) == 0 && (col & 15) == 0 && (bm.pitch & 15) == 0) {
         void* dp = nullptr;
         if (hipHostGetDevicePointer(&dp, const_cast<uint8_t*>(r->h), 0) == hipSuccess && dp)
             hdev = static_cast<const uint8_t*>(dp);
         else
             (void)hipGetLastError();
-    }
-    if (staged()) hdev = nullptr;   // pageable input: copied through the bounce buffers
-    const int npc = std::max<int>(1, std::min<int>(opt.nstreams, static_cast<int>((r->n + 4095) / 4096)));
-    if (staged() && r->n > 0) {
-        // the widest piece the loop below can cut, against the bounce size set at add_beam
-        const int64_t widest = (r->n + npc - 1) / npc + 15 * (npc - 1);
-        if (static_cast<size_t>((widest + 15) & ~int64_t{15}) * static_cast<size_t>(nchan) > bounce_bytes) {
-            r->status = fail(AA_EINVAL, "aa_stream_submit: staged piece exceeds the bounce buffers");
-            for (size_t j = 0; j < pieces.size(); ++j) arena.release(offs[j], need[j]);
-            return true;
-        }
     }
     std::vector<hipEvent_t> pev;
     std::vector<int64_t> pend;   // end column (exclusive) covered after piece i
@@ -298,51 +337,82 @@ bool aa_pipeline_s::try_issue(Request* r) {
         else w = r->n - src;
         if (w > 0 && staged()) {
             // host-to-host into a pinned bounce buffer (rows split over the stage threads),
-            // then the device copy from it; the buffer's previous copy must have finished
+            // then the device copy from it. The wait for the buffer's previous device copy
+            // and the host copies run with the pipeline lock released, so submit, poll and
+            // release callers are not blocked; add_beam waits for staging_active to clear
+            // before it may replace the bounce buffers.
             const unsigned j = bounce_next++ % static_cast<unsigned>(bounce.size());
-            if (bounce_ev[j]) (void)hipEventSynchronize(bounce_ev[j]);
             const int64_t bp = (w + 15) & ~int64_t{15};   // bp * nchan <= bounce_bytes, checked above
             uint8_t* hb = bounce[j];
+            const hipEvent_t prev_copy = bounce_ev[j];
             const uint8_t* hs = r->h + src;
             const int64_t sp = r->pitch;
             const int parts = std::min<int>(opt.nstreams, static_cast<int>(nchan));
-            stagers.run(parts, [&](int q) {
-                const int64_t c0 = nchan * q / parts, c1 = nchan * (q + 1) / parts;
-                for (int64_t c = c0; c < c1; ++c) std::memcpy(hb + c * bp, hs + c * sp, static_cast<size_t>(w));
-            });
-            void* dp = nullptr;
-            const bool mapped = hipHostGetDevicePointer(&dp, hb, 0) == hipSuccess && dp;
-            if (!mapped) (void)hipGetLastError();
-            const int64_t body = (mapped && (col & 15) == 0 && (bm.pitch & 15) == 0) ? (w & ~int64_t{15}) : 0;
-            if (body)
-                (void)launch_gather_rows(bm.buf[nb] + col, bm.pitch, static_cast<const uint8_t*>(dp), bp, body, nchan, cs);
-            if (w > body)
-                (void)hipMemcpy2DAsync(bm.buf[nb] + col + body, bm.pitch, hb + body, bp, w - body, nchan,
-                                       hipMemcpyHostToDevice, cs);
+            staging_active = true;
+            lk.unlock();
+            const hipError_t se = prev_copy ? hipEventSynchronize(prev_copy) : hipSuccess;
+            if (se == hipSuccess)
+                stagers.run(parts, [&](int q) {
+                    const int64_t c0 = nchan * q / parts, c1 = nchan * (q + 1) / parts;
+                    for (int64_t c = c0; c < c1; ++c) std::memcpy(hb + c * bp, hs + c * sp, static_cast<size_t>(w));
+                });
+            lk.lock();
+            staging_active = false;
+            cv_stage.notify_all();
+            if (ok(se, "pipeline: bounce buffer wait")) {
+                void* dp = nullptr;
+                const bool mapped = hipHostGetDevicePointer(&dp, hb, 0) == hipSuccess && dp;
+                if (!mapped) (void)hipGetLastError();
+                const int64_t body = (mapped && (col & 15) == 0 && (bm.pitch & 15) == 0) ? (w & ~int64_t{15}) : 0;
+                if (body)
+                    ok(launch_gather_rows(bm.buf[nb] + col, bm.pitch, static_cast<const uint8_t*>(dp), bp, body, nchan, cs) ==
+                               AA_OK ? hipSuccess : hipErrorLaunchFailure,
+                       "pipeline: staged row gather");
+                if (w > body)
+                    ok(hipMemcpy2DAsync(bm.buf[nb] + col + body, bm.pitch, hb + body, bp, w - body, nchan,
+                                        hipMemcpyHostToDevice, cs),
+                       "pipeline: staged copy");
+            }
             if (!bounce_ev[j]) bounce_ev[j] = get_event(false);
-            (void)hipEventRecord(bounce_ev[j], cs);
+            if (!bounce_ev[j] || !ok(hipEventRecord(bounce_ev[j], cs), "pipeline: event record")) {
+                (void)hipStreamSynchronize(cs);   // the buffer's copy must be over before its next fill
+                put_event(bounce_ev[j], false);
+                bounce_ev[j] = nullptr;
+            }
         } else if (w > 0) {
             if (hdev && (w & 15) == 0)
-                (void)launch_gather_rows(bm.buf[nb] + col, bm.pitch, hdev + src, r->pitch, w, nchan, cs);
+                ok(launch_gather_rows(bm.buf[nb] + col, bm.pitch, hdev + src, r->pitch, w, nchan, cs) == AA_OK
+                       ? hipSuccess : hipErrorLaunchFailure,
+                   "pipeline: row gather");
             else if (hdev) {   // 16-byte body by the kernel, ragged tail by the runtime copy
                 const int64_t body = w & ~int64_t{15};
-                if (body) (void)launch_gather_rows(bm.buf[nb] + col, bm.pitch, hdev + src, r->pitch, body, nchan, cs);
-                (void)hipMemcpy2DAsync(bm.buf[nb] + col + body, bm.pitch, r->h + src + body, r->pitch, w - body, nchan,
-                                       hipMemcpyHostToDevice, cs);
+                if (body)
+                    ok(launch_gather_rows(bm.buf[nb] + col, bm.pitch, hdev + src, r->pitch, body, nchan, cs) == AA_OK
+                           ? hipSuccess : hipErrorLaunchFailure,
+                       "pipeline: row gather");
+                ok(hipMemcpy2DAsync(bm.buf[nb] + col + body, bm.pitch, r->h + src + body, r->pitch, w - body, nchan,
+                                    hipMemcpyHostToDevice, cs),
+                   "pipeline: H2D copy");
             } else
-                (void)hipMemcpy2DAsync(bm.buf[nb] + col, bm.pitch, r->h + src, r->pitch, w, nchan,
-                                       hipMemcpyHostToDevice, cs);
+                ok(hipMemcpy2DAsync(bm.buf[nb] + col, bm.pitch, r->h + src, r->pitch, w, nchan, hipMemcpyHostToDevice, cs),
+                   "pipeline: H2D copy");
         }
         col += w;
         src += w;
         hipEvent_t ev = get_event(false);
-        (void)hipEventRecord(ev, cs);
+        if (!ev || !ok(hipEventRecord(ev, cs), "pipeline: event record")) {
+            put_event(ev, false);
+            ev = nullptr;   // sub-chunks that need this piece wait by synchronising the copy stream
+        }
         pev.push_back(ev);
         pend.push_back(col);
     }
     if (timing()) {
         r->c1 = get_event(true);
-        (void)hipEventRecord(r->c1, cs);
+        if (!r->c1 || !ok(hipEventRecord(r->c1, cs), "pipeline: event record")) {
+            put_event(r->c1, true);
+            r->c1 = nullptr;
+        }
     }
     bm.cur = nb;
     bm.h0 = h0n;
@@ -370,35 +440,68 @@ bool aa_pipeline_s::try_issue(Request* r) {
         uint8_t* blk = arena.base + u.off;
         int32_t* dplane = reinterpret_cast<int32_t*>(blk);
         blk += up(static_cast<size_t>(p->ndm) * opitch * 4);
-        void* work = blk;
+        void* work_buf = blk;
         blk += up(sps_work_bytes(p, u.b - u.a));
         aa_candidate_t* dcand = reinterpret_cast<aa_candidate_t*>(blk);
         blk += up(static_cast<size_t>(cap) * sizeof(aa_candidate_t));
         int32_t* dcount = reinterpret_cast<int32_t*>(blk);
+        uint8_t* hs = h_slots + static_cast<size_t>(u.slot) * slot_bytes;
+        std::memset(hs, 0, sizeof(int32_t));   // a chunk whose count copy fails reads 0, not a stale count
+        bool launch = true;
         if (u.stream >= 0) {
             size_t k = 0;
             while (k + 1 < pend.size() && pend[k] < w1 - h0n) ++k;
-            (void)hipStreamWaitEvent(s, pev[k], 0);
+            if (!pev[k] || !ok(hipStreamWaitEvent(s, pev[k], 0), "pipeline: compute stream wait")) {
+                // without the wait the kernels could read the history before its copy lands
+                if (!ok(hipStreamSynchronize(cs), "pipeline: copy stream synchronise")) launch = false;
+            }
         }
+        if (fault_unit >= 0 && units_issued == fault_unit) {
+            launch = false;
+            if (r->status == AA_OK || r->status == AA_EOVERFLOW) {
+                r->status = fail(AA_EHIP, "pipeline: injected fault (AA_FAULT) at sub-chunk " + std::to_string(units_issued));
+                r->err = aa_last_error();
+            }
+        }
+        ++units_issued;
         if (timing()) {
             u.k0 = get_event(true);
-            (void)hipEventRecord(u.k0, s);
+            if (u.k0 && !ok(hipEventRecord(u.k0, s), "pipeline: event record")) {
+                put_event(u.k0, true);
+                u.k0 = nullptr;
+            }
         }
-        int rc = launch_dedisperse(p, p->variant, bm.buf[nb] + (w0 - h0n), bm.pitch, n_in, dplane, opitch, s);
-        if (rc == AA_OK)
-            rc = launch_single_pulse(p, dplane, opitch, w0, n_out, u.a, u.b, t_total, work, dcand, cap, dcount,
-                                     nullptr, 0, s);
-        if (rc != AA_OK) r->status = rc;
+        if (launch) {
+            int rc = launch_dedisperse(p, p->variant, bm.buf[nb] + (w0 - h0n), bm.pitch, n_in, dplane, opitch, s);
+            if (rc == AA_OK)
+                rc = launch_single_pulse(p, dplane, opitch, w0, n_out, u.a, u.b, t_total, work_buf, dcand, cap, dcount,
+                                         nullptr, 0, s);
+            if (rc != AA_OK && (r->status == AA_OK || r->status == AA_EOVERFLOW)) {
+                r->status = rc;
+                r->err = aa_last_error();
+            }
+            if (rc == AA_OK) {
+                ok(hipMemcpyAsync(hs, dcount, sizeof(int32_t), hipMemcpyDeviceToHost, s), "pipeline: D2H count");
+                ok(hipMemcpyAsync(hs + kAlign, dcand, static_cast<size_t>(cap) * sizeof(aa_candidate_t),
+                                  hipMemcpyDeviceToHost, s),
+                   "pipeline: D2H candidates");
+            }
+        }
         if (timing()) {
             u.k1 = get_event(true);
-            (void)hipEventRecord(u.k1, s);
+            if (u.k1 && !ok(hipEventRecord(u.k1, s), "pipeline: event record")) {
+                put_event(u.k1, true);
+                u.k1 = nullptr;
+            }
         }
-        uint8_t* hs = h_slots + static_cast<size_t>(u.slot) * slot_bytes;
-        (void)hipMemcpyAsync(hs, dcount, sizeof(int32_t), hipMemcpyDeviceToHost, s);
-        (void)hipMemcpyAsync(hs + kAlign, dcand, static_cast<size_t>(cap) * sizeof(aa_candidate_t),
-                             hipMemcpyDeviceToHost, s);
         u.done = get_event(false);
-        (void)hipEventRecord(u.done, s);
+        if (!u.done || !ok(hipEventRecord(u.done, s), "pipeline: event record")) {
+            // no completion event: wait here (error path only) so the arena block and the
+            // result slot are not reused while the stream may still write them
+            (void)hipStreamSynchronize(s);
+            put_event(u.done, false);
+            u.done = nullptr;
+        }
     }
     // piece events are only waited on above, so they can be recycled now: a later record
     // on the same event does not change a wait already enqueued
@@ -410,14 +513,29 @@ bool aa_pipeline_s::try_issue(Request* r) {
     return true;
 }
 
+void aa_pipeline_s::log_result(const Request* r) {
+    if (!log) return;
+    std::fprintf(log,
+                 "{\"tag\": %llu, \"beam\": %d, \"t_begin\": %lld, \"t_end\": %lld, \"samples\": %lld, "
+                 "\"sub_chunks\": %zu, \"candidates\": %lld, \"status\": %d, \"queue_s\": %.6f, \"latency_s\": %.6f}\n",
+                 static_cast<unsigned long long>(r->tag), r->beam, static_cast<long long>(r->t_begin),
+                 static_cast<long long>(r->t_end), static_cast<long long>(r->n), r->units.size(),
+                 static_cast<long long>(r->n_true), r->status, r->t_admit - r->t_submit, r->t_done - r->t_submit);
+    std::fflush(log);
+}
+
 void aa_pipeline_s::complete_units() {
     for (size_t i = 0; i < inflight.size();) {
         Request* r = inflight[i];
         for (Unit& u : r->units) {
             if (u.complete) continue;
-            const hipError_t q = hipEventQuery(u.done);
+            // a unit without a completion event had its stream synchronised when it was issued
+            const hipError_t q = u.done ? hipEventQuery(u.done) : hipSuccess;
             if (q == hipErrorNotReady) continue;
-            if (q != hipSuccess) r->status = hip_fail(q, "pipeline: asynchronous failure");
+            if (q != hipSuccess) {
+                r->status = hip_fail(q, "pipeline: asynchronous failure");
+                r->err = aa_last_error();
+            }
             const uint8_t* hs = h_slots + static_cast<size_t>(u.slot) * slot_bytes;
             int32_t cnt = 0;
             std::memcpy(&cnt, hs, sizeof(cnt));
@@ -457,6 +575,7 @@ void aa_pipeline_s::complete_units() {
                 return x.dm_idx != y.dm_idx ? x.dm_idx < y.dm_idx : x.t < y.t;
             });
             r->t_done = now_s();
+            log_result(r);
             for (Beam& bm : beams)
                 for (auto& lu : bm.last_user)
                     if (lu == r) lu = nullptr;
@@ -477,21 +596,26 @@ void aa_pipeline_s::run() {
         bool progress = false;
         const size_t before = inflight.size() + queue.size();
         complete_units();
-        // admission: arrival order, in order per beam, head-of-line for resources
-        for (auto it = queue.begin(); it != queue.end();) {
-            Request* r = *it;
+        // admission: arrival order, in order per beam, head-of-line for resources. Requests
+        // are addressed by index: try_issue may release the lock (staged input), and a
+        // submit in that window appends to the queue, which invalidates deque iterators
+        // but not the positions of the requests already queued (only this thread erases).
+        for (size_t i = 0; i < queue.size();) {
+            Request* r = queue[i];
             Beam& bm = beams[r->beam];
             if (r->seq != bm.issued_seq) {   // an earlier chunk of this beam is still queued
-                ++it;
+                ++i;
                 continue;
             }
-            if (!try_issue(r)) {
+            if (!try_issue(r, lk)) {
                 if (inflight.empty()) {
                     // nothing in flight can release memory or slots: this request never fits
                     r->status = fail(AA_ENOMEM, "pipeline: chunk needs more arena memory or result slots than exist");
+                    r->err = aa_last_error();
                     ++bm.issued_seq;
-                    it = queue.erase(it);
+                    queue.erase(queue.begin() + static_cast<std::ptrdiff_t>(i));
                     r->t_admit = r->t_done = now_s();
+                    log_result(r);
                     done.push_back(r);
                     ++completed;
                     cv_done.notify_all();
@@ -501,7 +625,7 @@ void aa_pipeline_s::run() {
                 break;
             }
             ++bm.issued_seq;
-            it = queue.erase(it);
+            queue.erase(queue.begin() + static_cast<std::ptrdiff_t>(i));
             inflight.push_back(r);
             progress = true;
         }
@@ -526,15 +650,24 @@ extern "C" int aa_pipeline_create(const aa_pipeline_opts_t* opts, aa_pipeline_t*
     if (!p) return fail(AA_ENOMEM, "aa_pipeline_create: out of host memory");
     p->opt = o;
     p->cap = o.cand_cap;
+    if (o.min_piece_work != 0) p->min_piece_work = o.min_piece_work;
+    p->beams.reserve(static_cast<size_t>(o.max_beams));   // Beam references stay valid while the lock is released
+    if (const char* f = std::getenv("AA_FAULT")) {
+        if (std::strncmp(f, "unit:", 5) == 0) p->fault_unit = std::strtoll(f + 5, nullptr, 10);
+    }
     auto cleanup = [&](int rc) {
         if (p->d_arena) (void)hipFree(p->d_arena);
         if (p->h_slots) (void)hipHostFree(p->h_slots);
         if (p->copy) (void)hipStreamDestroy(p->copy);
         for (hipStream_t s : p->comp) (void)hipStreamDestroy(s);
         if (p->ref) (void)hipEventDestroy(p->ref);
+        if (p->log) std::fclose(p->log);
         delete p;
         return rc;
     };
+    if (const char* lp = std::getenv("AA_LOG")) {
+        if (*lp && !(p->log = std::fopen(lp, "a"))) return cleanup(fail(AA_EINVAL, "aa_pipeline_create: cannot open AA_LOG"));
+    }
     if (hipGetDevice(&p->device) != hipSuccess) return cleanup(fail(AA_EHIP, "aa_pipeline_create: no device"));
     // streams at the default priority (section 2, step 1)
     if (hipStreamCreateWithFlags(&p->copy, hipStreamNonBlocking) != hipSuccess)
@@ -588,16 +721,23 @@ int aa_pipeline_s::grow_bounce(size_t bytes) {
     return AA_OK;
 }
 
-extern "C" int aa_pipeline_add_beam(aa_pipeline_t p, aa_plan_t plan, int32_t* beam) {
+namespace {
+int add_beam(aa_pipeline_t p, aa_plan_t plan, int64_t t_resume, int32_t* beam) {
     if (!p || !plan || !beam) return fail(AA_EINVAL, "aa_pipeline_add_beam: null argument");
     if (plan->device != p->device) return fail(AA_EINVAL, "aa_pipeline_add_beam: plan is not on the pipeline's device");
     if (plan->nwidths > 32) return fail(AA_EINVAL, "aa_pipeline_add_beam: more than 32 widths");
-    std::lock_guard<std::mutex> g(p->mu);
+    if (t_resume < 0 || t_resume % plan->stat_block)
+        return fail(AA_EINVAL, "aa_pipeline_add_beam_at: t_resume must be a non-negative multiple of the stat block");
+    std::unique_lock<std::mutex> lk(p->mu);
     if (static_cast<int>(p->beams.size()) >= p->opt.max_beams) return fail(AA_EBUSY, "aa_pipeline_add_beam: max_beams reached");
     Beam b;
     b.plan = plan;
     b.cols = p->opt.max_chunk + plan->maxshift + plan->wmax + plan->stat_block + 32;
     b.pitch = static_cast<int64_t>(up(static_cast<size_t>(b.cols)));
+    // a resumed beam starts with an empty history whose column 0 is the left-halo column
+    // of its first start, rounded down to 16 samples: the first submit begins there
+    b.e = t_resume;
+    b.h0 = b.R = t_resume > 0 ? ((t_resume - 1) & ~int64_t{15}) : 0;
     const size_t bytes = static_cast<size_t>(b.pitch) * plan->nchan;
     if (!p->arena.alloc(bytes, &b.off[0])) return fail(AA_ENOMEM, "aa_pipeline_add_beam: HBM budget exhausted");
     if (!p->arena.alloc(bytes, &b.off[1])) {
@@ -613,6 +753,8 @@ extern "C" int aa_pipeline_add_beam(aa_pipeline_t p, aa_plan_t plan, int32_t* be
         // with a 16-byte pitch
         const int64_t piece = std::max<int64_t>((p->opt.max_chunk + p->opt.nstreams - 1) / p->opt.nstreams, 4096) +
                               16 * static_cast<int64_t>(p->opt.nstreams);
+        // the scheduler may be filling a bounce buffer with the lock released
+        p->cv_stage.wait(lk, [&] { return !p->staging_active; });
         const int rc = p->grow_bounce(static_cast<size_t>((piece + 15) & ~int64_t{15}) * plan->nchan);
         if (rc != AA_OK) {
             p->arena.release(b.off[0], bytes);
@@ -623,6 +765,16 @@ extern "C" int aa_pipeline_add_beam(aa_pipeline_t p, aa_plan_t plan, int32_t* be
     p->beams.push_back(b);
     *beam = static_cast<int32_t>(p->beams.size() - 1);
     return AA_OK;
+}
+}  // namespace
+
+extern "C" int aa_pipeline_add_beam(aa_pipeline_t p, aa_plan_t plan, int32_t* beam) {
+    return add_beam(p, plan, 0, beam);
+}
+
+extern "C" int aa_pipeline_add_beam_at(aa_pipeline_t p, aa_plan_t plan, int64_t t_resume, int32_t* beam) {
+    if (!plan) return fail(AA_EINVAL, "aa_pipeline_add_beam_at: null argument");
+    return add_beam(p, plan, t_resume, beam);
 }
 
 extern "C" int aa_stream_submit(aa_pipeline_t p, int32_t beam, const uint8_t* h_chunk, int64_t nsamp, int64_t pitch,
@@ -679,6 +831,7 @@ extern "C" int aa_poll(aa_pipeline_t p, aa_result_t* out, int32_t timeout_us) {
     out->cand = r->cand.data();
     out->latency_s = r->t_done - r->t_submit;
     out->queue_s = r->t_admit - r->t_submit;
+    if (r->status < 0) set_error(r->err);   // the chunk's failure, readable by the caller
     return AA_OK;
 }
 
@@ -775,6 +928,7 @@ extern "C" int aa_pipeline_destroy(aa_pipeline_t p) {
     for (hipEvent_t e : p->bounce_ev)
         if (e) (void)hipEventDestroy(e);
     for (uint8_t* b : p->bounce) (void)hipHostFree(b);
+    if (p->log) std::fclose(p->log);
     delete p;
     return AA_OK;
 }

@@ -35,11 +35,13 @@ def sig():
     return dict(x=x, host=host, pageable=np.ascontiguousarray(x), nchan=nchan, nsamp=nsamp, dms=dms, want=want)
 
 
-def _run(sig, chunk, nstreams, serial=False, cap=1 << 14, sdma=False, staged=False, pageable=False):
+def _run(sig, chunk, nstreams, serial=False, cap=1 << 14, sdma=False, staged=False, pageable=False, min_piece_work=-1):
+    """min_piece_work -1 (the default here) splits every chunk over all streams, as the
+    paper does, so that the sub-chunk edges are exercised at these small sizes."""
     from paper_2101_00941_amd import Pipeline, Plan
     plan = Plan(sig["nchan"], sig["nsamp"], F_TOP, FOFF, TSAMP, sig["dms"], WIDTHS, 6.0, 32768)
     pipe = Pipeline(nstreams=nstreams, max_beams=1, max_chunk=chunk, cand_cap=cap, hbm_budget=2 << 30,
-                    serial=serial, timing=True, sdma_copy=sdma, staged=staged)
+                    serial=serial, timing=True, sdma_copy=sdma, staged=staged, min_piece_work=min_piece_work)
     b = pipe.add_beam(plan)
     host, nsamp = (sig["pageable"] if pageable else sig["host"]), sig["nsamp"]
     tags = []
@@ -178,3 +180,92 @@ def test_hbm_budget_too_small_for_beam():
         pipe.add_beam(plan)
     assert e.value.code == -3
     pipe.close()
+
+
+@pytest.mark.parametrize("nstreams", [4, 8])
+def test_default_split_policy_matches(sig, nstreams):
+    """The default sub-chunk policy (no piece below 2^33 trial x channel x start units)
+    keeps these small chunks whole and spreads consecutive chunks over the streams."""
+    got, covered, st = _run(sig, 1 << 17, nstreams, min_piece_work=0)
+    assert_candidates_equal(got, sig["want"])
+
+
+def test_injected_fault_surfaces_on_its_tag(sig, tmp_path, monkeypatch):
+    """AA_FAULT=unit:K (read at create) skips the launch of the K-th sub-chunk: exactly
+    that chunk reports AA_EHIP on aa_poll, every other chunk's candidates are exact, and
+    AA_LOG records one line per chunk with its status. No kernel is faulted: the skipped
+    sub-chunk simply launches nothing."""
+    import json
+
+    from paper_2101_00941_amd import Pipeline, Plan
+    log = tmp_path / "chunks.jsonl"
+    monkeypatch.setenv("AA_FAULT", "unit:2")
+    monkeypatch.setenv("AA_LOG", str(log))
+    plan = Plan(sig["nchan"], sig["nsamp"], F_TOP, FOFF, TSAMP, sig["dms"], WIDTHS, 6.0, 32768)
+    pipe = Pipeline(nstreams=2, max_beams=1, max_chunk=1 << 17, hbm_budget=2 << 30, min_piece_work=-1)
+    monkeypatch.delenv("AA_FAULT")
+    monkeypatch.delenv("AA_LOG")
+    b = pipe.add_beam(plan)
+    host, nsamp, chunk = sig["host"], sig["nsamp"], 1 << 17
+    n = 0
+    for k, a in enumerate(range(0, nsamp, chunk)):
+        m = min(chunk, nsamp - a)
+        pipe.submit(b, host[:, a:a + m], nsamp=m, pitch=host.stride(0), tag=k, last=(a + m == nsamp))
+        n += 1
+    bad, good = [], []
+    for _ in range(n):
+        r = pipe.poll(timeout_us=20_000_000)
+        assert r is not None
+        if r["status"] != 0:
+            assert r["status"] == -4
+            bad.append((r["t_begin"], r["t_end"]))
+        else:
+            good.extend((int(c["dm_idx"]), int(c["t"]), int(c["width"]), float(c["snr"])) for c in r["cand"])
+    pipe.close()
+    assert len(bad) == 1
+    lo, hi = bad[0]
+    want = [c for c in sig["want"] if not lo <= c[1] < hi]
+    good = sorted((c for c in good if not lo <= c[1] < hi), key=lambda c: (c[0], c[1]))
+    assert_candidates_equal(good, want)
+    lines = [json.loads(x) for x in log.read_text().splitlines()]
+    assert len(lines) == n and sum(1 for x in lines if x["status"] == -4) == 1
+
+
+@pytest.mark.parametrize("cut_chunks", [1, 2])
+def test_checkpoint_resume_equals_uninterrupted(sig, cut_chunks):
+    """Stop a beam after some chunks and destroy its pipeline; a new pipeline resumes at
+    the last t_end (aa_pipeline_add_beam_at) with the samples from the resume column on.
+    The concatenated candidates equal the whole-signal oracle."""
+    from paper_2101_00941_amd import Pipeline, Plan
+    plan = Plan(sig["nchan"], sig["nsamp"], F_TOP, FOFF, TSAMP, sig["dms"], WIDTHS, 6.0, 32768)
+    host, nsamp, chunk = sig["host"], sig["nsamp"], 100_000
+    got, ckpt = [], 0
+    pipe = Pipeline(nstreams=2, max_beams=1, max_chunk=chunk, hbm_budget=2 << 30)
+    b = pipe.add_beam(plan)
+    for k in range(cut_chunks):
+        pipe.submit(b, host[:, k * chunk:(k + 1) * chunk], nsamp=chunk, pitch=host.stride(0), tag=k)
+    for _ in range(cut_chunks):
+        r = pipe.poll(timeout_us=20_000_000)
+        assert r is not None and r["status"] == 0
+        ckpt = max(ckpt, r["t_end"])
+        got.extend((int(c["dm_idx"]), int(c["t"]), int(c["width"]), float(c["snr"])) for c in r["cand"])
+    pipe.close()
+    assert ckpt > 0 and ckpt % 32768 == 0
+    pipe = Pipeline(nstreams=3, max_beams=1, max_chunk=chunk, hbm_budget=2 << 30)
+    b = pipe.add_beam(plan, t_resume=ckpt)
+    a = (ckpt - 1) & ~15
+    tag, n = 100, 0
+    while a < nsamp:
+        m = min(chunk, nsamp - a)
+        pipe.submit(b, host[:, a:a + m], nsamp=m, pitch=host.stride(0), tag=tag, last=(a + m == nsamp))
+        a, tag, n = a + m, tag + 1, n + 1
+    first = None
+    for _ in range(n):
+        r = pipe.poll(timeout_us=20_000_000)
+        assert r is not None and r["status"] == 0
+        first = r["t_begin"] if first is None else min(first, r["t_begin"])
+        got.extend((int(c["dm_idx"]), int(c["t"]), int(c["width"]), float(c["snr"])) for c in r["cand"])
+    pipe.close()
+    assert first == ckpt
+    got.sort(key=lambda c: (c[0], c[1]))
+    assert_candidates_equal(got, sig["want"])
