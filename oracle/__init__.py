@@ -19,13 +19,15 @@ Modules:
   dedisp    D[d][t] = sum_c X[c][t + s[d][c]]
   sps       per-block moments, boxcar sums, S/N, best width, 3x3 peaks, candidates
   pipeline  whole-signal run and chunked run (section 1's time chunking)
+  decimate  per-range time decimation: halvings of the input, range plans, their run
 """
 
 from .plan import K_DM, channel_freqs, shift_table, sizes
 from .dedisp import dedisperse, dedisperse_rows
 from .sps import block_moments, block_norms, best_plane, candidates, single_pulse
 from .pipeline import run, run_chunked
+from .decimate import decimate, decimate2, range_plans, run_ranges
 
 __all__ = ["K_DM", "channel_freqs", "shift_table", "sizes", "dedisperse", "dedisperse_rows",
            "block_moments", "block_norms", "best_plane", "candidates", "single_pulse",
-           "run", "run_chunked"]
+           "run", "run_chunked", "decimate", "decimate2", "range_plans", "run_ranges"]
