@@ -8,10 +8,19 @@ boxcar S/N, 3x3 peaks and ordered candidates), then the asynchronous copy of the
 candidate count and list to pinned host memory.
 
 Prints ONE JSON line with the metric, a roofline object for the dominant kernel
-(dedispersion, measured with HIP events on its own stream), and the CPU oracle
-timed on a bounded sample of the same workload.
+(dedispersion, measured with HIP events on its own stream), the best shift-and-add
+(no matrix core) variant beside it, the CPU oracle timed on a bounded sample of the
+same workload, and two compact sub-objects for the rest of the metric:
+  streamed  the streamed pipeline (pinned host input in 2^18-sample chunks) against
+            the plain single-stream path: hidden-transfer fraction H, efficiency E and
+            wall time per stream count, on the 128-channel signal and on the survey
+            signal (16 chunks), with the streamed survey's candidates checked against
+            the resident run's;
+  serving   32 beams with Poisson arrivals at 1x and 4x real time: p50/p99 chunk
+            latency and throughput of continuous batching against the plain FIFO path.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-extras]
+       python bench.py --mode streamed|serving|batched   (the full runs of each form)
 """
 
 from __future__ import annotations
@@ -37,62 +46,100 @@ ALU_PEAK_TOPS = 2 * CU * LANES * CLOCK_GHZ / 1000.0   # 78.6 T byte-adds/s
 I8_MFMA_PEAK_TOPS = 5000.0
 # HBM bytes per launch of the dedispersion kernel (FETCH_SIZE x 2.000 + WRITE_SIZE x
 # 1.000 per dispatch, scaled by a 1 GiB copy), from the counter runs summarised in
-# profiles/dedisp_*_survey_4096ch_1M.md. Keyed by (workload, variant); valid only for
-# the kernel code those counters were taken on.
+# profiles/dedisp_*_survey_4096ch_1M.md. Keyed by (workload, variant), with the digest of
+# the kernel sources the counters were taken on: after any change to those sources the
+# entry no longer matches and the bench reports traffic as null.
 TRAFFIC_BYTES = {
-    ("survey_4096ch_1M", 12): 175.5e9 + 12.15e9,
-    ("survey_4096ch_1M", 17): 279.1e9 + 12.15e9,
-    ("survey_4096ch_1M", 20): 202.0e9 + 12.15e9,
+    ("survey_4096ch_1M", 12): (175.5e9 + 12.15e9, "e36571f09499436e"),
+    ("survey_4096ch_1M", 17): (279.1e9 + 12.15e9, "e36571f09499436e"),
+    ("survey_4096ch_1M", 20): (202.0e9 + 12.15e9, "e36571f09499436e"),
 }
+KERNEL_SOURCES = ("dedisp.hip", "tiling.cpp", "aa_internal.h", "xcd.h")
+
+
+def kernel_digest():
+    """sha256 (16 hex digits) of the dedispersion kernel sources with comments and blank
+    space removed, so that comment edits keep a counter entry valid and code edits do not."""
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2101_00941_amd", "csrc", name)) as f:
+            text = f.read()
+        text = re.sub(r"//[^\n]*", "", text)
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        h.update(re.sub(r"\s+", " ", text).strip().encode())
+    return h.hexdigest()[:16]
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-_CPU = {}
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
-def _cpu_triple(centre):
-    """Oracle on one triple of neighbouring trials: dedisperse rows centre-1..centre+1 over
-    the full time range, then search the centre row (it needs both neighbours)."""
-    import oracle
-    w, x, s, sz = _CPU["w"], _CPU["x"], _CPU["s"], _CPU["sz"]
-    rows = [centre - 1, centre, centre + 1]
-    t0 = time.perf_counter()
-    D = oracle.dedisperse_rows(x, s, rows, w["nsamp"], sz["maxshift"])
-    oracle.single_pulse(D, 0, 0, sz["n_start"], sz["n_start"], w["widths"], w["threshold"], w["stat_block"],
-                        row0=rows[0], ndm=len(w["dms"]), report_rows=[centre])
-    return time.perf_counter() - t0
+def cpu_baseline(w, x, threads=None, groups=None, rows_per_group=4):
+    """Time the oracle (as it is) on a bounded sample of the workload, on the host's cores.
 
-
-def cpu_baseline(w, x, n_centres=10):
-    """Time the oracle (as it is) on a bounded sample: `n_centres` DM trials spread evenly
-    over the plan (every ndm / n_centres-th), each searched over the full time range with
-    its two neighbour rows dedispersed as well. The triples run in a thread pool over the
-    host's cores (at most 16 threads); numpy is single-threaded here. value counts only the
-    searched centre rows. Threads, not processes: the oracle's large numpy operations
-    release the GIL, and no process forks after the GPU is initialised."""
+    The sample is `groups` runs of `rows_per_group` consecutive DM trials, spread evenly
+    over the plan. Each run dedisperses its trials and the two neighbour trials (the 3x3
+    peak test needs them) over the full time range, then searches its trials over every
+    start. Phase 1 times all dedispersion rows in a thread pool, phase 2 all searches
+    (numpy releases the GIL in its large operations; threads, since no process may fork
+    after the GPU is initialised). Reported:
+      dedisp_rate  dedispersed rows x samples / phase-1 wall time
+      search_rate  searched rows x starts / phase-2 wall time
+      value        the whole plan's rate on these cores when every trial is dedispersed
+                   once and searched once: N_dd / (t_dd per row + t_search per row)."""
     from concurrent.futures import ThreadPoolExecutor
 
     import oracle
+    ncpu = os.cpu_count() or 1
+    threads = threads or max(1, min(16, ncpu))
+    groups = groups or threads
     ndm = len(w["dms"])
-    step = ndm // n_centres
-    centres = [min(max(1, step // 2 + k * step), ndm - 2) for k in range(n_centres)]
+    step = ndm // groups
+    starts = [min(max(1, step // 2 + k * step), ndm - rows_per_group - 1) for k in range(groups)]
     s = oracle.shift_table(w["dms"], w["nchan"], w["f_top"], w["foff"], w["tsamp"])
     sz = oracle.sizes(s, w["nsamp"], w["widths"], w["stat_block"])
-    _CPU.update(w=w, x=x, s=s, sz=sz)
-    cores = max(1, min(16, os.cpu_count() or 1, n_centres))
+    rows = sorted({r for a in starts for r in range(a - 1, a + rows_per_group + 1)})
+
+    def dd_row(r):
+        return r, oracle.dedisperse_rows(x, s, [r], w["nsamp"], sz["maxshift"])[0]
+
     t0 = time.perf_counter()
-    with ThreadPoolExecutor(cores) as pool:
-        per = list(pool.map(_cpu_triple, centres))
-    wall = time.perf_counter() - t0
-    cpu = float(sum(per))
-    return dict(value=n_centres * sz["n_dd"] / wall, unit="DM-trial*samples/s", cores=cores, kind="oracle",
-                per_triple_value=n_centres * sz["n_dd"] / cpu,
-                sample=f"{n_centres} DM trials (every {step}th: {centres[0]}..{centres[-1]}), each with its 2 neighbour "
-                       f"rows dedispersed, x {sz['n_dd']} samples, dedispersion + single-pulse search, numpy, "
-                       f"{cores} threads, {wall:.1f} s wall, {cpu:.1f} s summed over the triples")
+    with ThreadPoolExecutor(threads) as pool:
+        D = dict(pool.map(dd_row, rows))
+    t_dd = time.perf_counter() - t0
+
+    def search(a):
+        lo = a - 1
+        plane = np.stack([D[r] for r in range(lo, a + rows_per_group + 1)])
+        oracle.single_pulse(plane, 0, 0, sz["n_start"], sz["n_start"], w["widths"], w["threshold"], w["stat_block"],
+                            row0=lo, ndm=ndm, report_rows=list(range(a, a + rows_per_group)))
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as pool:
+        list(pool.map(search, starts))
+    t_sps = time.perf_counter() - t0
+    n_dd_rows, n_sps_rows = len(rows), groups * rows_per_group
+    per_row = t_dd / n_dd_rows + t_sps / n_sps_rows
+    return dict(value=sz["n_dd"] / per_row, unit="DM-trial*samples/s", cores=threads, kind="oracle",
+                dedisp_rate=n_dd_rows * sz["n_dd"] / t_dd, search_rate=n_sps_rows * sz["n_start"] / t_sps,
+                host_cpus=ncpu, cpu_model=_cpu_model(),
+                sample=f"{groups} runs of {rows_per_group} consecutive DM trials spread over the plan (first trials "
+                       f"{starts[0]}..{starts[-1]}); {n_dd_rows} trials dedispersed (runs plus neighbours) x "
+                       f"{sz['n_dd']} samples in {t_dd:.1f} s, {n_sps_rows} trials searched x {sz['n_start']} starts in "
+                       f"{t_sps:.1f} s; numpy oracle, {threads} threads on {ncpu} host CPUs")
 
 
 def h2d_probe(torch, nchan, ncols, pitch):
@@ -115,13 +162,78 @@ def h2d_probe(torch, nchan, ncols, pitch):
     return out
 
 
-def streamed(a):
-    """Streamed mode: a pinned host signal fed chunk by chunk through aa_stream_submit.
-    Runs the plain single-stream pipeline and then S = 1, 2, 4, 8 compute streams, and
-    reports end-to-end rates, copy/kernel/overlap time and the hidden-transfer share."""
+def stream_run(plan, src, nsamp, chunk, S, serial=False, sdma=False, staged=False, budget=16 << 30, cap=1 << 14,
+               src_cols=None, reps=2, want_cands=False):
+    """One beam streamed through a pipeline: `nsamp` samples in chunks of `chunk`, read
+    from `src` (uint8 [nchan, >= src_cols], pinned torch tensor or pageable numpy array).
+    With src_cols < nsamp the source columns repeat: chunk k reads columns
+    (k * chunk) mod src_cols. The first of `reps` passes warms copy engines and kernels;
+    the last is reported. Returns wall time, union lengths of copy and kernel intervals
+    (HIP events), H = overlap / copy union, E = max(copy union, kernel union) / span."""
     import torch
 
-    from paper_2101_00941_amd import Pipeline, Plan
+    from paper_2101_00941_amd import Pipeline
+    src_cols = src_cols or nsamp
+    pitch = src.stride(0) if hasattr(src, "stride") and callable(src.stride) else src.strides[0]
+    out = None
+    for _ in range(reps):
+        pipe = Pipeline(nstreams=S, max_beams=1, max_chunk=chunk, cand_cap=cap, hbm_budget=budget, serial=serial,
+                        timing=True, sdma_copy=sdma, staged=staged)
+        b = pipe.add_beam(plan)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nk = 0
+        for k, s0 in enumerate(range(0, nsamp, chunk)):
+            n = min(chunk, nsamp - s0)
+            c0 = s0 % src_cols
+            assert c0 + n <= src_cols
+            pipe.submit(b, src[:, c0:c0 + n], nsamp=n, pitch=pitch, tag=k, last=(s0 + n == nsamp))
+            nk += 1
+        ncand, cands, bad = 0, [], 0
+        for _ in range(nk):
+            r = pipe.poll(timeout_us=60_000_000)
+            assert r is not None, "pipeline stalled"
+            bad += r["status"] not in (0, -5)
+            ncand += r["n_true"]
+            if want_cands:
+                cands.extend((int(c["dm_idx"]), int(c["t"]), int(c["width"]), float(c["snr"])) for c in r["cand"])
+        wall = time.perf_counter() - t0
+        st = pipe.stats()
+        pipe.close()
+        assert bad == 0, "a chunk failed"
+        out = dict(wall_ms=wall * 1e3, candidates=ncand, **st)
+        if want_cands:
+            out["cand_list"] = sorted(cands, key=lambda c: (c[0], c[1]))
+    out["hidden_frac"] = out["overlap_ms"] / out["copy_ms"] if out["copy_ms"] > 0 else None
+    out["efficiency"] = max(out["copy_ms"], out["kernel_ms"]) / out["span_ms"] if out["span_ms"] > 0 else None
+    return out
+
+
+def _stream_rows(plan, host, nsamp, chunk, modes, budget, cap, src_cols=None, pageable=None):
+    rows = []
+    for mode, S, serial, sdma, is_pageable, staged in modes:
+        src = pageable if is_pageable else host
+        r = stream_run(plan, src, nsamp, chunk, S, serial, sdma, staged, budget, cap, src_cols)
+        r.update(mode=mode, nstreams=S)
+        r["dm_trial_samples_per_s"] = plan.info["ndm"] * (nsamp - plan.info["maxshift"]) / (r["wall_ms"] * 1e-3)
+        rows.append(r)
+        log(f"[bench] {mode} S={S}: {r['wall_ms']:.1f} ms wall, copy {r['copy_ms']:.1f} ms, kernels "
+            f"{r['kernel_ms']:.1f} ms, overlap {r['overlap_ms']:.1f} ms, hidden {r['hidden_frac']}, "
+            f"E {r['efficiency']}, {r['candidates']} candidates")
+    plain = next(r["wall_ms"] for r in rows if r["mode"] == "plain")
+    for r in rows:
+        r["speedup_vs_plain"] = plain / r["wall_ms"]
+    return rows
+
+
+def streamed(a):
+    """Streamed mode: a pinned host signal fed chunk by chunk through aa_stream_submit.
+    Runs the paper's "before" mode (pageable input, no streams), the plain single-stream
+    pipeline and then S = 1, 2, 4, 8 compute streams, and reports end-to-end rates,
+    copy/kernel/overlap time and the hidden-transfer share."""
+    import torch
+
+    from paper_2101_00941_amd import Plan
     from synth.workloads import make_input, workload
 
     w = workload(a.workload)
@@ -138,9 +250,7 @@ def streamed(a):
     plan = Plan.from_workload(w)
     if a.variant != "auto":
         plan.set_variant(int(a.variant))
-    ndm = plan.info["ndm"]
     budget = int(a.budget_gb * (1 << 30))
-    rows = []
     # pageable copy of the same signal, for the paper's "before" mode (pageable input, no
     # streams) and for the pipeline's staged pageable input
     pageable = np.array(host.numpy(), copy=True)
@@ -148,45 +258,68 @@ def streamed(a):
     modes = ([("pageable-default", 1, True, False, True, False), ("plain", 1, True, False, False, False)]
              + [("streams", s, False, False, False, False) for s in (1, 2, 4, 8)]
              + [("streams-sdma", 2, False, True, False, False), ("pageable-staged", 4, False, False, True, True)])
-    for mode, S, serial, sdma, is_pageable, staged in modes:
-        best = None
-        src_arr = pageable if is_pageable else host
-        for rep in range(2):   # first pass warms up copy engines and kernels
-            pipe = Pipeline(nstreams=S, max_beams=1, max_chunk=chunk, cand_cap=a.stream_cap, hbm_budget=budget,
-                            serial=serial, timing=True, sdma_copy=sdma, staged=staged)
-            b = pipe.add_beam(plan)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            nk = 0
-            for k, s0 in enumerate(range(0, nsamp, chunk)):
-                n = min(chunk, nsamp - s0)
-                pipe.submit(b, src_arr[:, s0:s0 + n], nsamp=n, pitch=nsamp, tag=k, last=(s0 + n == nsamp))
-                nk += 1
-            ncand = 0
-            for _ in range(nk):
-                r = pipe.poll(timeout_us=60_000_000)
-                assert r is not None and r["status"] in (0, -5), r
-                ncand += r["n_true"]
-            wall = time.perf_counter() - t0
-            st = pipe.stats()
-            pipe.close()
-            best = dict(mode=mode, nstreams=S, wall_ms=wall * 1e3, candidates=ncand, **st)
-        T = plan.info["n_start"]
-        best["dm_trial_samples_per_s"] = ndm * (nsamp - plan.info["maxshift"]) / (best["wall_ms"] * 1e-3)
-        best["samples_per_s"] = nsamp / (best["wall_ms"] * 1e-3)
-        best["hidden_frac"] = best["overlap_ms"] / best["copy_ms"] if best["copy_ms"] > 0 else None
-        best["efficiency"] = (max(best["copy_sum_ms"], best["kernel_sum_ms"]) / best["span_ms"]
-                              if best["span_ms"] > 0 else None)
-        rows.append(best)
-        log(f"[bench] {mode} S={S}: {best['wall_ms']:.1f} ms wall, copy {best['copy_ms']:.1f} ms, "
-            f"kernels {best['kernel_ms']:.1f} ms, overlap {best['overlap_ms']:.1f} ms, "
-            f"hidden {best['hidden_frac']}, {best['candidates']} candidates")
-    plain = next(r["wall_ms"] for r in rows if r["mode"] == "plain")
-    for r in rows:
-        r["speedup_vs_plain"] = plain / r["wall_ms"]
-    return dict(workload=w["name"], chunk=chunk, ndm=ndm, nchan=nchan, nsamp=nsamp, dedisp_variant=plan.variant,
-                h2d_probe=probe,
+    rows = _stream_rows(plan, host, nsamp, chunk, modes, budget, a.stream_cap, pageable=pageable)
+    return dict(workload=w["name"], chunk=chunk, ndm=plan.info["ndm"], nchan=nchan, nsamp=nsamp,
+                dedisp_variant=plan.variant, h2d_probe=probe,
                 hw_queues=os.environ.get("GPU_MAX_HW_QUEUES", "default"), runs=rows)
+
+
+def streamed_compact(variant, budget_gb, cap, survey_host=None, resident_cands=None):
+    """The streamed part of the default bench line.
+    * streamed_128ch_8M: the 128-channel signal, 2^23 samples in 2^18 chunks (32 chunks).
+    * survey_4096ch_streamed_16x: the survey plan over 16 chunks of 2^18 samples, read
+      cyclically from the resident run's 2^20-sample pinned input. Its candidates over
+      the starts that the first 2^20 samples determine must equal the resident run's."""
+    import torch
+
+    from paper_2101_00941_amd import Plan
+    from synth.workloads import make_input, workload
+
+    out = {}
+    budget = int(budget_gb * (1 << 30))
+    base = [("plain", 1, True, False, False, False)] + [("streams", s, False, False, False, False) for s in (1, 2, 4, 8)]
+    w = workload("streamed_128ch_8M")
+    host = torch.empty((w["nchan"], w["nsamp"]), dtype=torch.uint8).pin_memory()
+    make_input(w, out=host.numpy())
+    plan = Plan.from_workload(w)
+    plan.set_variant(variant)
+    log(f"[bench] streamed {w['name']}")
+    rows = _stream_rows(plan, host, w["nsamp"], w["chunk"], base, budget, cap)
+    out[w["name"]] = _compact_rows(rows, chunks=w["nsamp"] // w["chunk"])
+    del host
+    if survey_host is not None:
+        ws = workload("survey_4096ch_1M")
+        plan = Plan.from_workload(ws)
+        plan.set_variant(variant)
+        chunk, nchunks = 1 << 18, 16
+        log(f"[bench] streamed survey plan, {nchunks} chunks of {chunk}")
+        modes = [("plain", 1, True, False, False, False)] + [("streams", s, False, False, False, False) for s in (2, 4)]
+        rows = _stream_rows(plan, survey_host, nchunks * chunk, chunk, modes, budget, cap, src_cols=ws["nsamp"])
+        res = _compact_rows(rows, chunks=nchunks)
+        if resident_cands is not None:
+            # starts below e = the first block-aligned start whose boxcars or right
+            # neighbour reach past the first 2^20 samples are determined by them alone
+            e = (ws["nsamp"] - plan.info["wmax"] - plan.info["maxshift"]) // plan.info["stat_block"] * plan.info["stat_block"]
+            r = stream_run(plan, survey_host, 4 * chunk, chunk, 4, budget=budget, cap=cap, src_cols=ws["nsamp"], reps=1,
+                           want_cands=True)
+            got = [c for c in r["cand_list"] if c[1] < e]
+            want = [c for c in resident_cands if c[1] < e]
+            res["check"] = {"starts": e, "candidates": len(want),
+                            "identical_to_resident": [c[:3] for c in got] == [c[:3] for c in want]
+                            and all(abs(g[3] - h[3]) <= 1e-5 * max(1.0, abs(h[3])) for g, h in zip(got, want))}
+            log(f"[bench] streamed survey vs resident over starts < {e}: {res['check']}")
+        out["survey_4096ch_streamed_16x"] = res
+    return out
+
+
+def _compact_rows(rows, chunks):
+    keep = ("wall_ms", "speedup_vs_plain", "hidden_frac", "efficiency", "copy_ms", "kernel_ms", "overlap_ms",
+            "span_ms", "dm_trial_samples_per_s")
+    out = {"chunks": chunks}
+    for r in rows:
+        key = r["mode"] if r["mode"] == "plain" else f"S{r['nstreams']}"
+        out[key] = {k: (round(r[k], 4) if isinstance(r[k], float) else r[k]) for k in keep}
+    return out
 
 
 def serving(a):
@@ -344,6 +477,10 @@ def main():
     ap.add_argument("--hw-queues", type=int, default=0, help="GPU_MAX_HW_QUEUES for this process (<= 32)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (reference kernel for HBM counters)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="resident run only: leave out the compact streamed and serving runs")
+    ap.add_argument("--serve-compact-s", type=float, default=6.0,
+                    help="seconds of Poisson arrivals per serving run in the default bench line")
     a = ap.parse_args()
     if a.hw_queues:
         # HIP maps streams onto this many hardware queues; it must be set before HIP starts
@@ -443,15 +580,18 @@ def main():
     adds = ndm * n_dd * nchan
     achieved = adds / (ms_dedisp * 1e-3) / 1e12
     value = ndm * n_dd / (ms_step * 1e-3)
-    vinfo = Plan.variants()[plan.variant]
-    traffic = TRAFFIC_BYTES.get((w["name"], plan.variant)) if not a.ndm else None
+    variants = Plan.variants()
+    vinfo = variants[plan.variant]
+    entry = TRAFFIC_BYTES.get((w["name"], plan.variant)) if not a.ndm else None
+    traffic = entry[0] if entry and entry[1] == kernel_digest() else None
     if vinfo["layout"] in (4, 5, 6):
         # a contraction on the i8 matrix cores, priced against their dense peak; one op
         # per useful byte add (the one-hot weights are not counted)
         roofline = {"bound": "mfma", "dtype": "i8", "kernel": "dedisp_kernel (i8 matrix cores)",
                     "achieved": achieved, "peak": I8_MFMA_PEAK_TOPS, "unit": "TOP/s",
                     "frac": achieved / I8_MFMA_PEAK_TOPS, "traffic": traffic, "per_launch_ops": adds,
-                    "ms_per_launch": ms_dedisp, "alu_peak": ALU_PEAK_TOPS, "alu_frac": achieved / ALU_PEAK_TOPS}
+                    "ms_per_launch": ms_dedisp, "alu_peak": ALU_PEAK_TOPS, "alu_frac": achieved / ALU_PEAK_TOPS,
+                    "hbm_frac": (ndm * n_dd * 4 + nchan * w["nsamp"]) / (ms_dedisp * 1e-3) / (HBM_PEAK_GBS * 1e9)}
     else:
         roofline = {"bound": "alu", "kernel": "dedisp_kernel", "achieved": achieved, "peak": ALU_PEAK_TOPS,
                     "unit": "TOP/s", "frac": achieved / ALU_PEAK_TOPS, "traffic": traffic,
@@ -477,10 +617,94 @@ def main():
         "kernels_ms": {"dedisperse": ms_dedisp, "single_pulse": ms_sps},
         "candidates": int(h_count.item()),
     }
+    if a.variant == "auto":
+        # the best variant without matrix cores (shift-and-add in LDS, layouts 0-3), from
+        # the same autotune pass (one timed launch each), priced against the VALU add peak
+        sa = [(m, v) for v, m in enumerate(ms) if m > 0 and variants[v]["layout"] in (0, 1, 2, 3)]
+        if sa:
+            m, v = min(sa)
+            ach = adds / (m * 1e-3) / 1e12
+            res["shift_and_add"] = {"variant": v, "ms_per_launch": m, "achieved": ach, "peak": ALU_PEAK_TOPS,
+                                    "unit": "TOP/s", "frac": ach / ALU_PEAK_TOPS, "bound": "alu",
+                                    "value_if_used": ndm * n_dd / ((m + ms_sps) * 1e-3)}
+    if not a.no_extras and not a.ndm and w["name"] == "survey_4096ch_1M":
+        res["decimated"] = decimated_run(w, x, plan.variant, stream)
     if not a.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         res["cpu_baseline"] = cpu_baseline(w, x_np[:, :w["nsamp"]])
+    if not a.no_extras and not a.ndm:
+        n = min(int(h_count.item()), a.cap)
+        raw = h_cand[: n * 24].numpy().view(_cand_dtype())
+        resident = [(int(r["dm_idx"]), int(r["t"]), int(r["width"]), float(r["snr"])) for r in raw]
+        del dd, work, x
+        torch.cuda.empty_cache()
+        res["streamed"] = streamed_compact(plan.variant, a.budget_gb, a.stream_cap, survey_host=x_host,
+                                           resident_cands=resident)
+        res["serving"] = serving_compact(a, plan.variant)
     print(json.dumps(res), flush=True)
+
+
+SURVEY_RANGES = ([0, 512, 1024, 1536, 2048, 2432], [1, 2, 4, 8, 16, 32])
+
+
+def decimated_run(w, x, variant, stream, steps=5):
+    """Per-range time decimation on the resident survey input: the plan's six DM ranges
+    (steps 1/16 .. 2) at factors 1, 2, 4, .. 32, one aa_range_run per step (decimation,
+    dedispersion and search of every range). Reports ms per run (HIP events on the
+    launch stream), the input-sample rate and the adds it performs."""
+    import torch
+
+    from paper_2101_00941_amd import RangePlan
+    first, factor = SURVEY_RANGES
+    rp = RangePlan(w["nchan"], w["nsamp"], w["f_top"], w["foff"], w["tsamp"], w["dms"], w["widths"], w["threshold"],
+                   first, factor, w["stat_block"])
+    rp.set_variant(variant)
+    cap = 1 << 20
+    work = torch.empty(rp.work_bytes(w["nsamp"], cap), dtype=torch.uint8, device=x.device)
+    cand = torch.empty(cap * 24, dtype=torch.uint8, device=x.device)
+    count = torch.zeros(1, dtype=torch.int32, device=x.device)
+    for _ in range(2):
+        rp.run(x, n_in=w["nsamp"], cap=cap, work=work, cand=cand, count=count)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        rp.run(x, n_in=w["nsamp"], cap=cap, work=work, cand=cand, count=count)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    ndm = len(w["dms"])
+    adds = 0
+    for r, f in enumerate(factor):
+        hi = first[r + 1] if r + 1 < len(first) else ndm
+        adds += (hi - first[r]) * (w["nsamp"] // f) * w["nchan"]
+    out = {"ranges_first": first, "factors": factor, "ms_per_run": ms, "candidates": int(count.item()),
+           "input_samples_per_s": ndm * w["nsamp"] / (ms * 1e-3), "adds_per_run": adds,
+           "adds_vs_plain": adds / (ndm * w["nsamp"] * w["nchan"]), "dedisp_variant": variant}
+    log(f"[bench] decimated ranges: {ms:.2f} ms per run, {out['candidates']} candidates, "
+        f"{out['adds_vs_plain']:.3f} of the plain adds")
+    del work, cand, count, rp
+    return out
+
+
+def _cand_dtype():
+    from paper_2101_00941_amd import _native
+    return _native.CANDIDATE_DTYPE
+
+
+def serving_compact(a, variant):
+    """The serving part of the default bench line: serving_32beams for a.serve_compact_s
+    seconds of arrivals at 1x and 4x real time, continuous batching against plain FIFO."""
+    import copy
+    b = copy.copy(a)
+    b.serve_seconds, b.rate_scale, b.budget_gb, b.beams = a.serve_compact_s, [1.0, 4.0], 200.0, 32
+    b.variant = str(variant)
+    full = serving(b)
+    out = {"beams": full["beams"], "seconds": full["seconds"], "streams": full["streams"],
+           "hbm_budget_gb": full["hbm_budget_gb"], "dedisp_variant": full["dedisp_variant"]}
+    for k, r in full["results"].items():
+        out[k] = {q: round(r[q], 4) for q in ("p50_ms", "p99_ms", "mean_ms", "dm_trial_samples_per_s")}
+        out[k]["chunks"] = r["chunks"]
+    return out
 
 
 if __name__ == "__main__":

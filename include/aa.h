@@ -194,6 +194,45 @@ int aa_single_pulse(aa_plan_t plan, const int32_t* d_dd, int64_t dd_pitch, int64
                     void* d_work, size_t work_bytes, aa_candidate_t* d_cand, int32_t cap,
                     int32_t* d_count, float* d_best, int64_t best_pitch, void* stream);
 
+/* ---- per-range time decimation --------------------------------------------------
+ * Beyond the paper, whose dedispersion phase (section 2.1) is brute force at the input
+ * resolution. The trials are split into consecutive ranges; range r (first trial
+ * first[r], first[0] = 0) is dedispersed and searched on the input decimated by
+ * factor[r] = 2^k: k halvings, each the rounding average of adjacent samples,
+ *   y[c][j] = (x[c][2j] + x[c][2j+1] + 1) >> 1,  0 <= j < floor(n / 2),
+ * at sampling time factor[r] * tsamp. Each range is an ordinary plan (aa_plan with the
+ * range's trials, nsamp >> k, tsamp * factor[r] and stat_block / factor[r]; the same
+ * widths, in the range's samples, and threshold): its own maxshift, N_dd and T, and a
+ * 3x3 peak test that does not look across the range's edges. Candidates are reported in
+ * input samples: dm_idx is the global trial index, t = factor[r] * (range start) and
+ * width = factor[r] * (range width), sorted by (dm_idx, t).
+ *   aa_decimate2       one halving of nchan rows (16-byte aligned buffers and pitches,
+ *                      out_pitch >= n_in / 2), asynchronous on `stream`.
+ *   aa_range_plan      validates the ranges (1..16; first[] ascending below ndm; factors
+ *                      powers of two, non-decreasing, dividing the stat block) and builds
+ *                      the per-range plans. AA_EINVAL otherwise; AA_ESHORT if a range is
+ *                      too short for its maxshift and widest boxcar at desc->nsamp.
+ *   aa_range_plan_get  the plan of range r (owned by the range plan: set its variant or
+ *                      autotune it; do not destroy it), its first trial and factor.
+ *   aa_range_work_bytes  scratch for aa_range_run on n_in input samples and capacity cap:
+ *                      the decimated inputs, one plane and one search scratch shared by
+ *                      the ranges in turn, and the ranges' candidate lists.
+ *   aa_range_run       all ranges over d_in (uint8 [nchan][in_pitch], n_in samples) on
+ *                      `stream`: *d_count receives the true total, d_cand the first cap
+ *                      candidates. AA_ESHORT if a range is too short at n_in.
+ */
+typedef struct aa_range_plan_s* aa_range_plan_t;
+
+int aa_decimate2(const uint8_t* d_in, int64_t in_pitch, int64_t n_in, int32_t nchan, uint8_t* d_out,
+                 int64_t out_pitch, void* stream);
+int aa_range_plan(const aa_plan_desc_t* desc, const int32_t* first, const int32_t* factor, int32_t nranges,
+                  aa_range_plan_t* out);
+int aa_range_plan_get(aa_range_plan_t rp, int32_t r, aa_plan_t* plan, int32_t* first, int32_t* factor);
+int aa_range_work_bytes(aa_range_plan_t rp, int64_t n_in, int32_t cap, size_t* out);
+int aa_range_run(aa_range_plan_t rp, const uint8_t* d_in, int64_t in_pitch, int64_t n_in, void* d_work,
+                 size_t work_bytes, aa_candidate_t* d_cand, int32_t cap, int32_t* d_count, void* stream);
+void aa_range_plan_destroy(aa_range_plan_t rp);
+
 /* ---- batched beams in one persistent launch ---------------------------------------
  * Many independent beams of uneven shape (nchan, nsamp, DM plan) are searched together.
  * The dedispersion of every beam in a group is ONE persistent launch: resident

@@ -122,6 +122,12 @@ def lib():
         "aa_batch_run": (C.c_int, [C.POINTER(BatchBeam), i32, i32, vp, sz, vp, i32, vp, C.c_uint32,
                                    C.POINTER(BatchInfo), vp]),
         "aa_single_pulse": (C.c_int, [vp, vp, i64, i64, i64, i64, i64, i64, vp, sz, vp, i32, vp, vp, i64, vp]),
+        "aa_decimate2": (C.c_int, [vp, i64, i64, i32, vp, i64, vp]),
+        "aa_range_plan": (C.c_int, [C.POINTER(PlanDesc), C.POINTER(i32), C.POINTER(i32), i32, C.POINTER(vp)]),
+        "aa_range_plan_get": (C.c_int, [vp, i32, C.POINTER(vp), C.POINTER(i32), C.POINTER(i32)]),
+        "aa_range_work_bytes": (C.c_int, [vp, i64, i32, C.POINTER(sz)]),
+        "aa_range_run": (C.c_int, [vp, vp, i64, i64, vp, sz, vp, i32, vp, vp]),
+        "aa_range_plan_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

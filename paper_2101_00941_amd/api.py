@@ -181,6 +181,84 @@ class Plan:
         return cand, count, best
 
 
+def decimate2(x, n_in=None, out=None, stream=None):
+    """aa_decimate2: one rounding-average halving of every row of a uint8 CUDA tensor."""
+    import torch
+    n_in = x.shape[1] if n_in is None else int(n_in)
+    if out is None:
+        out = torch.empty((x.shape[0], (n_in // 2 + 255) // 256 * 256), dtype=torch.uint8, device=x.device)
+    N.check(N.lib().aa_decimate2(_ptr(x), x.stride(0), n_in, x.shape[0], _ptr(out), out.stride(0),
+                                 _stream_handle(stream)))
+    return out
+
+
+class RangePlan:
+    """aa_range_plan: per-range time decimation over one plan description."""
+
+    def __init__(self, nchan, nsamp, f_top, foff, tsamp, dms, widths, threshold, first, factor, stat_block=0):
+        self._dm = np.ascontiguousarray(np.asarray(dms, dtype=np.float64))
+        self._w = np.ascontiguousarray(np.asarray(widths, dtype=np.int32))
+        d = N.PlanDesc()
+        d.nchan, d.nsamp = int(nchan), int(nsamp)
+        d.f_top_mhz, d.foff_mhz, d.tsamp_s = float(f_top), float(foff), float(tsamp)
+        d.dm = self._dm.ctypes.data_as(C.POINTER(C.c_double))
+        d.ndm = len(self._dm)
+        d.widths = self._w.ctypes.data_as(C.POINTER(C.c_int32))
+        d.nwidths = len(self._w)
+        d.snr_threshold = float(threshold)
+        d.stat_block = int(stat_block)
+        d.flags = 0
+        fa = (C.c_int32 * len(first))(*[int(v) for v in first])
+        fb = (C.c_int32 * len(factor))(*[int(v) for v in factor])
+        h = C.c_void_p()
+        N.check(N.lib().aa_range_plan(C.byref(d), fa, fb, len(first), C.byref(h)))
+        self._h = h
+        self.nchan = int(nchan)
+        self.first = [int(v) for v in first]
+        self.factor = [int(v) for v in factor]
+
+    def range_plan(self, r):
+        """(plan handle, first trial, factor) of range r; the handle stays owned here."""
+        p, a, f = C.c_void_p(), C.c_int32(), C.c_int32()
+        N.check(N.lib().aa_range_plan_get(self._h, int(r), C.byref(p), C.byref(a), C.byref(f)))
+        return p, a.value, f.value
+
+    def set_variant(self, v):
+        for r in range(len(self.first)):
+            N.check(N.lib().aa_plan_set_variant(self.range_plan(r)[0], int(v)))
+
+    def work_bytes(self, n_in, cap):
+        v = C.c_size_t()
+        N.check(N.lib().aa_range_work_bytes(self._h, int(n_in), int(cap), C.byref(v)))
+        return v.value
+
+    def run(self, x, n_in=None, cap=1 << 16, work=None, cand=None, count=None, stream=None):
+        """aa_range_run. Returns (cand uint8 [cap*24] tensor, count int32 [1] tensor)."""
+        import torch
+        n_in = x.shape[1] if n_in is None else int(n_in)
+        wb = self.work_bytes(n_in, cap)
+        if work is None or work.numel() < wb:
+            work = torch.empty(wb, dtype=torch.uint8, device=x.device)
+        if cand is None:
+            cand = torch.empty(max(cap, 1) * 24, dtype=torch.uint8, device=x.device)
+        if count is None:
+            count = torch.zeros(1, dtype=torch.int32, device=x.device)
+        N.check(N.lib().aa_range_run(self._h, _ptr(x), x.stride(0), n_in, _ptr(work), work.numel(), _ptr(cand),
+                                     int(cap), _ptr(count), _stream_handle(stream)))
+        return cand, count
+
+    def close(self):
+        if getattr(self, "_h", None):
+            N.lib().aa_range_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def candidates_to_numpy(cand, count, cap=None):
     """Copy a candidate buffer to the host as a structured array (dm_idx, width, t, snr, beam)."""
     n = int(count.item()) if hasattr(count, "item") else int(count)

@@ -171,6 +171,9 @@ DedispArgs dedisp_args(const aa_plan_s* p, int variant, const uint8_t* d_in, int
 int launch_dedisperse_batch(int variant, const DedispArgs* d_args, const int64_t* d_item_begin, int nbeams,
                             int64_t total, unsigned long long* d_counter, int max_row, hipStream_t stream);
 size_t sps_work_bytes(const aa_plan_s* p, int64_t n_starts);
+// One halving of each row: out[c][j] = (in[c][2j] + in[c][2j+1] + 1) >> 1, j < n_in / 2.
+int launch_halve(const uint8_t* in, int64_t in_pitch, int64_t n_in, int32_t nchan, uint8_t* out, int64_t out_pitch,
+                 hipStream_t stream);
 int launch_gather_rows(uint8_t* dst, int64_t dpitch, const uint8_t* src, int64_t spitch, int64_t width,
                        int64_t nrows, hipStream_t stream);
 int launch_single_pulse(const aa_plan_s* p, const int32_t* d_dd, int64_t dd_pitch, int64_t dd_t0,

@@ -18,7 +18,10 @@
 //    channels are folded per v_add3_u32 into packed u16x2 accumulators. A 16-bit
 //    half holds up to 257 * 255, so the pairs are widened into int32 accumulators
 //    every 256 channels.
-//  * No MFMA: this is shift-and-add, not a dense contraction.
+//  * The shift-and-add variants (layouts 0-3) use no matrix cores. The layouts 4-6
+//    variants below recast each block of 32 trials as an exact one-hot int8 contraction
+//    on the matrix cores (v_mfma_i32_32x32x32_i8), which is faster on this chip although
+//    most of its multiply-accumulates are by zero; see dedisp_mfma_tile.
 #include "aa_internal.h"
 #include "xcd.h"
 
