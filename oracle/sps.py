@@ -11,7 +11,15 @@ these readings:
   the exact count, sum and sum of squares over the block's starts:
       mu      = S1 / n                           (one rounding)
       var     = fl(n*S2 - S1^2) / (n*n)          (exact integer, then two roundings)
-      sigma   = sqrt(var)                        (population std, no clipping)
+      sigma   = sqrt(var)                        (population std)
+* Optional outlier clipping (clip_iters > 0 and clip_sigma > 0; robust statistics in
+  the spirit of the single-pulse search the paper cites): starting from all of the
+  block's values, each iteration computes mu and sigma as above from the values kept
+  so far, then keeps the block's values D with |float(D) - mu| <= c * sigma, where
+  c = float64(float32(clip_sigma)) and the product is one rounding; n, S1 and S2 are
+  then recomputed exactly over the kept values. If an iteration would keep no value,
+  the previous moments stay and clipping stops. The normalisation below uses the final
+  moments; the window sums and S/N are over all values, as without clipping.
 * Normalisation per block and width: wmu_w = w * mu and r_w = 1 / (sigma * sqrt(w)),
   where sqrt(w) is rounded first. If sigma == 0 then r_w = 0, so that S/N is 0.
 * S/N(d, t, w) = (float(sum_w) - wmu_w) * r_w. This is (sum - w mu) / (sigma sqrt w)
@@ -42,13 +50,34 @@ def block_moments(seg: np.ndarray):
     return n, s1, s2
 
 
-def block_norms(n: int, s1: list, s2: list, widths):
-    """Per row: (wmu [nw], r [nw]) as float64, following the module's rounding rules."""
+def clipped_moments(seg: np.ndarray, clip_sigma: float, clip_iters: int):
+    """Per row: exact (n, S1, S2) after the clipping iterations of the module header."""
+    c = float(np.float32(clip_sigma))
+    ns, s1s, s2s = [], [], []
+    for row in seg.astype(np.int64):
+        n, a, b = row.size, int(row.sum()), int((row * row).sum())
+        for _ in range(clip_iters):
+            mu = a / n
+            sigma = math.sqrt(float(n * b - a * a) / float(n * n))
+            keep = row[np.abs(row.astype(np.float64) - mu) <= c * sigma]
+            if keep.size == 0:
+                break
+            n, a, b = keep.size, int(keep.sum()), int((keep * keep).sum())
+        ns.append(n)
+        s1s.append(a)
+        s2s.append(b)
+    return ns, s1s, s2s
+
+
+def block_norms(n, s1: list, s2: list, widths):
+    """Per row: (wmu [nw], r [nw]) as float64, following the module's rounding rules.
+    n is the count shared by every row, or one count per row."""
     nw = len(widths)
     wmu = np.zeros((len(s1), nw))
     r = np.zeros((len(s1), nw))
     sqrtw = [math.sqrt(float(w)) for w in widths]
-    for i, (a, b) in enumerate(zip(s1, s2)):
+    nrow = [n] * len(s1) if isinstance(n, (int, np.integer)) else list(n)
+    for i, (a, b, n) in enumerate(zip(s1, s2, nrow)):
         mu = a / n                                   # exact rational, one rounding
         var = float(n * b - a * a) / float(n * n)
         sigma = math.sqrt(var)
@@ -101,7 +130,7 @@ def candidates(center, v_prev, v_same, v_next, threshold):
 
 def single_pulse(D: np.ndarray, dd_t0: int, t_begin: int, t_end: int, t_total: int, widths,
                  threshold: float, stat_block: int, row0: int = 0, ndm: int | None = None,
-                 report_rows=None, want_best: bool = False):
+                 report_rows=None, want_best: bool = False, clip_sigma: float = 0.0, clip_iters: int = 0):
     """Candidates for the starts [t_begin, t_end) of a dedispersed plane.
 
     D: int64 [nrows, ncols]. Row i is DM trial row0 + i, and column j is absolute
@@ -137,7 +166,10 @@ def single_pulse(D: np.ndarray, dd_t0: int, t_begin: int, t_end: int, t_total: i
     best_out = np.zeros((nrows, t_end - t_begin), dtype=np.float32) if want_best else None
     for b0 in range(t_begin, t_end, stat_block):
         b1 = min(b0 + stat_block, t_end)
-        n, s1, s2 = block_moments(D[:, b0 - dd_t0:b1 - dd_t0])
+        if clip_iters > 0 and clip_sigma > 0:
+            n, s1, s2 = clipped_moments(D[:, b0 - dd_t0:b1 - dd_t0], clip_sigma, clip_iters)
+        else:
+            n, s1, s2 = block_moments(D[:, b0 - dd_t0:b1 - dd_t0])
         wmu, r = block_norms(n, s1, s2, widths)
         lo = max(b0 - 1, 0)
         hi = b1 + 1 if (t_total < 0 or b1 + 1 <= t_total) else t_total
