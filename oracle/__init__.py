@@ -20,6 +20,7 @@ Modules:
   sps       per-block moments, boxcar sums, S/N, best width, 3x3 peaks, candidates
   pipeline  whole-signal run and chunked run (section 1's time chunking)
   decimate  per-range time decimation: halvings of the input, range plans, their run
+  cluster   cross-DM friends-of-friends clustering of a candidate list
 """
 
 from .plan import K_DM, channel_freqs, shift_table, sizes
@@ -27,7 +28,8 @@ from .dedisp import dedisperse, dedisperse_rows
 from .sps import block_moments, block_norms, best_plane, candidates, clipped_moments, single_pulse
 from .pipeline import run, run_chunked
 from .decimate import decimate, decimate2, range_plans, run_ranges
+from .cluster import cluster
 
 __all__ = ["K_DM", "channel_freqs", "shift_table", "sizes", "dedisperse", "dedisperse_rows",
            "block_moments", "block_norms", "best_plane", "candidates", "clipped_moments", "single_pulse",
-           "run", "run_chunked", "decimate", "decimate2", "range_plans", "run_ranges"]
+           "run", "run_chunked", "decimate", "decimate2", "range_plans", "run_ranges", "cluster"]
