@@ -61,7 +61,8 @@ const char* aa_version(void);
  * not ascending, unique and >= 1, wmax > AA_MAX_WIDTH, nchan*255*wmax >= 2^32
  * (boxcar sums are exact 32-bit integers), a stat block that is not a positive
  * multiple of 256 or that could overflow int64 moments, or a threshold that is not
- * finite. AA_ESHORT if T < 1. AA_EHIP or AA_ENOMEM if the upload fails.
+ * finite, a clip_sigma that is negative or not finite, or clip_iters outside 0..16.
+ * AA_ESHORT if T < 1. AA_EHIP or AA_ENOMEM if the upload fails.
  */
 #define AA_PLAN_HOST_ONLY 1u
 #define AA_MAX_WIDTH      1024
@@ -82,6 +83,9 @@ typedef struct {
     float         snr_threshold;  /* candidates need best S/N >= threshold           */
     int32_t       stat_block;     /* starts per statistics block; 0 means 32768      */
     uint32_t      flags;          /* AA_PLAN_HOST_ONLY                               */
+    float         clip_sigma;     /* outlier clipping of the block statistics, in sigma;
+                                     0 = off (see aa_single_pulse)                   */
+    int32_t       clip_iters;     /* clipping rounds, 0..16; 0 = off                 */
 } aa_plan_desc_t;
 
 typedef struct {
@@ -162,6 +166,11 @@ int aa_autotune(aa_plan_t plan, const uint8_t* d_in, int64_t in_pitch, int64_t n
  *     start 0. n, S1 and S2 are exact. mu = S1/n.
  *     var = double(n*S2 - S1^2) / double(n*n), where the integer is exact and is
  *     rounded once. sigma = sqrt(var).
+ *     With the plan's clip_sigma c > 0 and clip_iters k > 0 (robust statistics; the
+ *     paper defers its search to the single-pulse work it cites): k rounds, each
+ *     keeping the block's values D with |double(D) - mu| <= double(c) * sigma and
+ *     recomputing exact n, S1, S2, mu and sigma over the kept values; a round that
+ *     would keep nothing ends the clipping. Window sums still use every value.
  *     wmu_w = w*mu. r_w = 1/(sigma*sqrt(w)), or 0 if sigma == 0.
  *   - S/N(d,t,w) = (double(sum_{i<w} D[d][t+i]) - wmu_w) * r_w. best = max over w,
  *     and wbest is the smallest width that attains it.
@@ -232,6 +241,28 @@ int aa_range_work_bytes(aa_range_plan_t rp, int64_t n_in, int32_t cap, size_t* o
 int aa_range_run(aa_range_plan_t rp, const uint8_t* d_in, int64_t in_pitch, int64_t n_in, void* d_work,
                  size_t work_bytes, aa_candidate_t* d_cand, int32_t cap, int32_t* d_count, void* stream);
 void aa_range_plan_destroy(aa_range_plan_t rp);
+
+/* ---- cross-DM candidate clustering (host) -------------------------------------
+ * Beyond the paper (its search, section 2.2, defers to the single-pulse work it cites,
+ * which merges the detections of one pulse over neighbouring trials and starts).
+ * Friends of friends: two candidates of the same beam are linked iff their dm_idx differ
+ * by at most dm_radius and their t by at most t_radius; a cluster is a connected
+ * component. Each cluster reports its peak (the member with the highest snr; among equal
+ * snr the smallest (dm_idx, t)), its member count and the trial and start ranges of its
+ * members. Clusters are written in (beam, peak dm_idx, peak t) order.
+ * h_cand: host candidates, any order. h_out: host [cap]. *n_clusters: the true count.
+ * Errors: AA_EINVAL for negative sizes or radii; AA_EOVERFLOW if more than cap clusters
+ * (the first cap are written); AA_ENOMEM if host memory runs out.
+ */
+typedef struct {
+    aa_candidate_t peak;
+    int32_t members;
+    int32_t dm_lo, dm_hi;
+    int64_t t_lo, t_hi;
+} aa_cluster_t;
+
+int aa_cluster(const aa_candidate_t* h_cand, int64_t n, int32_t dm_radius, int64_t t_radius, aa_cluster_t* h_out,
+               int64_t cap, int64_t* n_clusters);
 
 /* ---- batched beams in one persistent launch ---------------------------------------
  * Many independent beams of uneven shape (nchan, nsamp, DM plan) are searched together.

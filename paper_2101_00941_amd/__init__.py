@@ -6,7 +6,7 @@ same names. See api.Plan.
 """
 
 from ._native import AAError, CANDIDATE_DTYPE, LIB_PATH, lib
-from .api import Pipeline, Plan, RangePlan, batch_run, candidates_as_tuples, candidates_to_numpy, decimate2
+from .api import Pipeline, Plan, RangePlan, batch_run, candidates_as_tuples, candidates_to_numpy, cluster, decimate2
 
 __all__ = ["AAError", "CANDIDATE_DTYPE", "LIB_PATH", "lib", "Pipeline", "Plan", "RangePlan", "batch_run",
-           "candidates_as_tuples", "candidates_to_numpy", "decimate2"]
+           "candidates_as_tuples", "candidates_to_numpy", "cluster", "decimate2"]

@@ -26,7 +26,8 @@ class PlanDesc(C.Structure):
     _fields_ = [("nchan", C.c_int32), ("nsamp", C.c_int64), ("f_top_mhz", C.c_double),
                 ("foff_mhz", C.c_double), ("tsamp_s", C.c_double), ("dm", C.POINTER(C.c_double)),
                 ("ndm", C.c_int32), ("widths", C.POINTER(C.c_int32)), ("nwidths", C.c_int32),
-                ("snr_threshold", C.c_float), ("stat_block", C.c_int32), ("flags", C.c_uint32)]
+                ("snr_threshold", C.c_float), ("stat_block", C.c_int32), ("flags", C.c_uint32),
+                ("clip_sigma", C.c_float), ("clip_iters", C.c_int32)]
 
 
 class PlanInfo(C.Structure):
@@ -73,6 +74,11 @@ class BatchBeam(C.Structure):
 class BatchInfo(C.Structure):
     _fields_ = [("groups", C.c_int32), ("variant", C.c_int32), ("items", C.c_int64), ("ms_dedisp", C.c_float),
                 ("ms_search", C.c_float), ("tuned_beam", C.c_int32), ("tune_ms", C.c_float * 32)]
+
+
+CLUSTER_DTYPE = np.dtype([("peak", CANDIDATE_DTYPE), ("members", "<i4"), ("dm_lo", "<i4"), ("dm_hi", "<i4"),
+                          ("pad", "<i4"), ("t_lo", "<i8"), ("t_hi", "<i8")])
+assert CLUSTER_DTYPE.itemsize == 56
 
 
 class AAError(RuntimeError):
@@ -123,6 +129,7 @@ def lib():
                                    C.POINTER(BatchInfo), vp]),
         "aa_single_pulse": (C.c_int, [vp, vp, i64, i64, i64, i64, i64, i64, vp, sz, vp, i32, vp, vp, i64, vp]),
         "aa_decimate2": (C.c_int, [vp, i64, i64, i32, vp, i64, vp]),
+        "aa_cluster": (C.c_int, [vp, i64, i32, i64, vp, i64, C.POINTER(i64)]),
         "aa_range_plan": (C.c_int, [C.POINTER(PlanDesc), C.POINTER(i32), C.POINTER(i32), i32, C.POINTER(vp)]),
         "aa_range_plan_get": (C.c_int, [vp, i32, C.POINTER(vp), C.POINTER(i32), C.POINTER(i32)]),
         "aa_range_work_bytes": (C.c_int, [vp, i64, i32, C.POINTER(sz)]),

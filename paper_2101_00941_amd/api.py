@@ -27,7 +27,8 @@ def _ptr(t):
 class Plan:
     """aa_plan: float64 shift table, sizes and the one-time device upload."""
 
-    def __init__(self, nchan, nsamp, f_top, foff, tsamp, dms, widths, threshold, stat_block=0, host_only=False):
+    def __init__(self, nchan, nsamp, f_top, foff, tsamp, dms, widths, threshold, stat_block=0, host_only=False,
+                 clip_sigma=0.0, clip_iters=0):
         L = N.lib()
         self._dm = np.ascontiguousarray(np.asarray(dms, dtype=np.float64))
         self._w = np.ascontiguousarray(np.asarray(widths, dtype=np.int32))
@@ -44,6 +45,8 @@ class Plan:
         d.snr_threshold = float(threshold)
         d.stat_block = int(stat_block)
         d.flags = N.AA_PLAN_HOST_ONLY if host_only else 0
+        d.clip_sigma = float(clip_sigma)
+        d.clip_iters = int(clip_iters)
         h = C.c_void_p()
         N.check(L.aa_plan(C.byref(d), C.byref(h)))
         self._h = h
@@ -195,7 +198,8 @@ def decimate2(x, n_in=None, out=None, stream=None):
 class RangePlan:
     """aa_range_plan: per-range time decimation over one plan description."""
 
-    def __init__(self, nchan, nsamp, f_top, foff, tsamp, dms, widths, threshold, first, factor, stat_block=0):
+    def __init__(self, nchan, nsamp, f_top, foff, tsamp, dms, widths, threshold, first, factor, stat_block=0,
+                 clip_sigma=0.0, clip_iters=0):
         self._dm = np.ascontiguousarray(np.asarray(dms, dtype=np.float64))
         self._w = np.ascontiguousarray(np.asarray(widths, dtype=np.int32))
         d = N.PlanDesc()
@@ -208,6 +212,8 @@ class RangePlan:
         d.snr_threshold = float(threshold)
         d.stat_block = int(stat_block)
         d.flags = 0
+        d.clip_sigma = float(clip_sigma)
+        d.clip_iters = int(clip_iters)
         fa = (C.c_int32 * len(first))(*[int(v) for v in first])
         fb = (C.c_int32 * len(factor))(*[int(v) for v in factor])
         h = C.c_void_p()
@@ -257,6 +263,19 @@ class RangePlan:
             self.close()
         except Exception:
             pass
+
+
+def cluster(cand, dm_radius, t_radius):
+    """aa_cluster over a host structured candidate array (CANDIDATE_DTYPE). Returns a
+    structured array of clusters (peak, members, dm_lo, dm_hi, t_lo, t_hi)."""
+    cand = np.ascontiguousarray(cand, dtype=N.CANDIDATE_DTYPE)
+    n = len(cand)
+    cap = max(n, 1)
+    out = np.zeros(cap, dtype=N.CLUSTER_DTYPE)
+    m = C.c_int64()
+    N.check(N.lib().aa_cluster(cand.ctypes.data_as(C.c_void_p) if n else None, n, int(dm_radius), int(t_radius),
+                               out.ctypes.data_as(C.c_void_p), cap, C.byref(m)))
+    return out[: m.value].copy()
 
 
 def candidates_to_numpy(cand, count, cap=None):

@@ -138,6 +138,8 @@ struct aa_plan_s {
     int64_t nsamp = 0, maxshift = 0, n_dd = 0, n_start = 0, nblocks = 0;
     double f_top = 0, foff = 0, tsamp = 0;
     float threshold = 0;
+    float clip_sigma = 0;                 // outlier clipping of the block statistics (0: off)
+    int32_t clip_iters = 0;
     uint32_t flags = 0;
     std::vector<double> dm;
     std::vector<int32_t> widths;

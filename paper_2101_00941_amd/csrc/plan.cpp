@@ -98,6 +98,8 @@ extern "C" int aa_plan(const aa_plan_desc_t* desc, aa_plan_t* out) {
     if (static_cast<uint64_t>(q.nchan) * 255u * static_cast<uint64_t>(wmax) >= (1ull << 32))
         return fail(AA_EINVAL, "aa_plan: nchan*255*wmax must stay below 2^32");
     if (!std::isfinite(q.snr_threshold)) return fail(AA_EINVAL, "aa_plan: threshold must be finite");
+    if (!std::isfinite(q.clip_sigma) || q.clip_sigma < 0 || q.clip_iters < 0 || q.clip_iters > 16)
+        return fail(AA_EINVAL, "aa_plan: clip_sigma must be finite and >= 0, clip_iters 0..16");
     const int32_t B = q.stat_block == 0 ? 32768 : q.stat_block;
     if (B < kSpsTile || B % kSpsTile) return fail(AA_EINVAL, "aa_plan: stat_block must be a positive multiple of 256");
     {
@@ -118,6 +120,8 @@ extern "C" int aa_plan(const aa_plan_desc_t* desc, aa_plan_t* out) {
     p->foff = q.foff_mhz;
     p->tsamp = q.tsamp_s;
     p->threshold = q.snr_threshold;
+    p->clip_sigma = q.clip_sigma;
+    p->clip_iters = q.clip_sigma > 0 ? q.clip_iters : 0;
     p->flags = q.flags;
     p->dm.assign(q.dm, q.dm + q.ndm);
     p->widths.assign(q.widths, q.widths + q.nwidths);

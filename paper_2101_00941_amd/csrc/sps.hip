@@ -59,58 +59,89 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
 }
 
 // ---- statistics -------------------------------------------------------------
+// Exact count, sum and sum of squares over the block's values that pass keep(v),
+// reduced over the work-group; the totals are returned to every thread.
+template <class Keep>
+__device__ __forceinline__ void block_moments(const int32_t* row, int64_t lo, int64_t hi, Keep keep, uint64_t* n_out,
+                                              uint64_t* s1_out, uint64_t* s2_out) {
+    uint64_t s1 = 0, s2 = 0, cnt = 0;
+    // elements up to the first 16-byte boundary, then 4 per lane, then the tail
+    const uint32_t* p = reinterpret_cast<const uint32_t*>(row + lo);
+    const int64_t n = hi - lo;
+    const int64_t head = min<int64_t>(static_cast<int64_t>(((16u - (reinterpret_cast<uintptr_t>(p) & 15u)) & 15u) >> 2), n);
+    const int64_t n4 = (n - head) >> 2;
+    auto add = [&](uint32_t v) {
+        if (keep(v)) {
+            s1 += v;
+            s2 += static_cast<uint64_t>(v) * v;
+            ++cnt;
+        }
+    };
+    if (threadIdx.x < head) add(p[threadIdx.x]);
+    const u32x4_t* q = reinterpret_cast<const u32x4_t*>(p + head);
+    for (int64_t i = threadIdx.x; i < n4; i += 256) {
+        const u32x4_t v = q[i];
+        add(v[0]);
+        add(v[1]);
+        add(v[2]);
+        add(v[3]);
+    }
+    for (int64_t t = head + 4 * n4 + threadIdx.x; t < n; t += 256) add(p[t]);
+    s1 = wave_sum_u64(s1);
+    s2 = wave_sum_u64(s2);
+    cnt = wave_sum_u64(cnt);
+    __shared__ uint64_t part[3][4];
+    const int wave = threadIdx.x >> 6;
+    __syncthreads();   // part[] may still be read from a previous call
+    if ((threadIdx.x & 63) == 0) {
+        part[0][wave] = s1;
+        part[1][wave] = s2;
+        part[2][wave] = cnt;
+    }
+    __syncthreads();
+    *s1_out = part[0][0] + part[0][1] + part[0][2] + part[0][3];
+    *s2_out = part[1][0] + part[1][1] + part[1][2] + part[1][3];
+    *n_out = part[2][0] + part[2][1] + part[2][2] + part[2][3];
+}
+
+// mu and sigma from exact moments, with the rounding points of the definition
+__device__ __forceinline__ void mu_sigma(uint64_t n, uint64_t s1, uint64_t s2, double* mu, double* sigma) {
+    *mu = static_cast<double>(s1) / static_cast<double>(n);
+    const unsigned __int128 num = static_cast<unsigned __int128>(n) * s2 - static_cast<unsigned __int128>(s1) * s1;
+    *sigma = __builtin_sqrt(u128_to_double_rn(num) / static_cast<double>(n * n));
+}
+
+// Per (stat block j, DM row d): exact moments, optionally clipped (clip_iters rounds of
+// keeping the values within clip_c * sigma of mu, recomputing exact moments over the
+// kept values; a round that would keep nothing ends the clipping), then the per-width
+// normalisation and each width's smallest passing window sum.
 __global__ __launch_bounds__(256) void sps_stats_kernel(const int32_t* __restrict__ dd, int64_t dd_pitch,
                                                         int64_t dd_t0, int64_t t_begin, int64_t t_end,
                                                         int32_t B, int32_t ndm, SpsConst sc,
-                                                        double threshold, double* __restrict__ norms,
-                                                        uint32_t* __restrict__ smin,
+                                                        double threshold, double clip_c, int32_t clip_iters,
+                                                        double* __restrict__ norms, uint32_t* __restrict__ smin,
                                                         int32_t* __restrict__ rowcount) {
     const int j = blockIdx.x;
     const int d = blockIdx.y;
     const int64_t lo = t_begin + static_cast<int64_t>(j) * B;
     const int64_t hi = min(lo + B, t_end);
     const int32_t* row = dd + static_cast<int64_t>(d) * dd_pitch - dd_t0;
-    uint64_t s1 = 0, s2 = 0;
-    // elements up to the first 16-byte boundary, then 4 per lane, then the tail
-    const uint32_t* p = reinterpret_cast<const uint32_t*>(row + lo);
-    const int64_t n = hi - lo;
-    const int64_t head = min<int64_t>(static_cast<int64_t>(((16u - (reinterpret_cast<uintptr_t>(p) & 15u)) & 15u) >> 2), n);
-    const int64_t n4 = (n - head) >> 2;
-    if (threadIdx.x < head) {
-        const uint32_t v = p[threadIdx.x];
-        s1 += v;
-        s2 += static_cast<uint64_t>(v) * v;
+    uint64_t n, s1, s2;
+    block_moments(row, lo, hi, [](uint32_t) { return true; }, &n, &s1, &s2);
+    double mu, sigma;
+    mu_sigma(n, s1, s2, &mu, &sigma);
+    for (int it = 0; it < clip_iters; ++it) {
+        const double lim = clip_c * sigma;
+        uint64_t m, a, b;
+        block_moments(row, lo, hi, [=](uint32_t v) { return __builtin_fabs(static_cast<double>(v) - mu) <= lim; }, &m,
+                      &a, &b);
+        if (m == 0) break;   // uniform: every thread holds the same totals
+        n = m;
+        s1 = a;
+        s2 = b;
+        mu_sigma(n, s1, s2, &mu, &sigma);
     }
-    const u32x4_t* q = reinterpret_cast<const u32x4_t*>(p + head);
-    for (int64_t i = threadIdx.x; i < n4; i += 256) {
-        const u32x4_t v = q[i];
-        s1 += static_cast<uint64_t>(v[0]) + v[1] + v[2] + v[3];
-        s2 += static_cast<uint64_t>(v[0]) * v[0] + static_cast<uint64_t>(v[1]) * v[1] +
-              static_cast<uint64_t>(v[2]) * v[2] + static_cast<uint64_t>(v[3]) * v[3];
-    }
-    for (int64_t t = head + 4 * n4 + threadIdx.x; t < n; t += 256) {
-        const uint32_t v = p[t];
-        s1 += v;
-        s2 += static_cast<uint64_t>(v) * v;
-    }
-    s1 = wave_sum_u64(s1);
-    s2 = wave_sum_u64(s2);
-    __shared__ uint64_t part[2][4];
-    const int wave = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        part[0][wave] = s1;
-        part[1][wave] = s2;
-    }
-    __syncthreads();
     if (threadIdx.x == 0) {
-        s1 = part[0][0] + part[0][1] + part[0][2] + part[0][3];
-        s2 = part[1][0] + part[1][1] + part[1][2] + part[1][3];
-        const uint64_t n = static_cast<uint64_t>(hi - lo);
-        const double mu = static_cast<double>(s1) / static_cast<double>(n);
-        const unsigned __int128 num = static_cast<unsigned __int128>(n) * s2 -
-                                      static_cast<unsigned __int128>(s1) * s1;
-        const double var = u128_to_double_rn(num) / static_cast<double>(n * n);
-        const double sigma = __builtin_sqrt(var);
         double* out = norms + (static_cast<int64_t>(j) * ndm + d) * (2 * sc.nw);
         uint32_t* so = smin + (static_cast<int64_t>(j) * ndm + d) * sc.nw;
         for (int k = 0; k < sc.nw; ++k) {
@@ -555,7 +586,8 @@ int launch_single_pulse(const aa_plan_s* p, const int32_t* d_dd, int64_t dd_pitc
     }
     hipLaunchKernelGGL(sps_stats_kernel, dim3(static_cast<unsigned>(L.nblk), static_cast<unsigned>(p->ndm)), dim3(256),
                        0, stream, d_dd, dd_pitch, dd_t0, t_begin, t_end, p->stat_block, p->ndm, sc,
-                       static_cast<double>(p->threshold), norms, smin, rowcount);
+                       static_cast<double>(p->threshold), static_cast<double>(p->clip_sigma),
+                       p->clip_sigma > 0.0f ? p->clip_iters : 0, norms, smin, rowcount);
     AA_HIP(hipGetLastError());
     const unsigned rowblocks = static_cast<unsigned>((p->ndm + kSpsRows - 1) / kSpsRows);
     if (L.ntiles * static_cast<int64_t>(rowblocks) > 0x7fffffff)

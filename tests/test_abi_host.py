@@ -138,3 +138,12 @@ def test_u128_to_double_matches_python(tmp_path):
     out = subprocess.run([str(exe)], input=inp, capture_output=True, text=True, check=True).stdout.split()
     for v, s in zip(vals, out):
         assert float.fromhex(s) == float(v), v
+
+
+def test_plan_rejects_bad_clipping():
+    from paper_2101_00941_amd import AAError, Plan
+    for c, it in ((-1.0, 2), (float("nan"), 1), (3.0, 17), (3.0, -1)):
+        with pytest.raises(AAError):
+            Plan(64, 20000, 1500.0, 1.5, 64e-6, np.arange(10.0), [1, 2], 6.0, clip_sigma=c, clip_iters=it,
+                 host_only=True)
+    Plan(64, 20000, 1500.0, 1.5, 64e-6, np.arange(10.0), [1, 2], 6.0, clip_sigma=3.0, clip_iters=16, host_only=True)
