@@ -203,6 +203,27 @@ int aa_single_pulse(aa_plan_t plan, const int32_t* d_dd, int64_t dd_pitch, int64
                     void* d_work, size_t work_bytes, aa_candidate_t* d_cand, int32_t cap,
                     int32_t* d_count, float* d_best, int64_t best_pitch, void* stream);
 
+/* ---- single-pulse search without allocation ----------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, and harnesses that forbid hipMalloc. The same search as
+ * aa_single_pulse, with the same arguments, results and errors, minus d_work: its
+ * scratch is a fixed array of AA_NOALLOC_SCRATCH_BYTES in the library's device
+ * memory, one per GPU, held until the process ends. The call allocates nothing (no
+ * hipMalloc, hipFree or allocating library routine); on its first call on a device it
+ * looks up that device's copy of the array once.
+ * Limit: aa_single_pulse_work_bytes(plan, t_end - t_begin) must not exceed
+ * AA_NOALLOC_SCRATCH_BYTES, else AA_EINVAL (search fewer starts per call, or use
+ * aa_single_pulse).
+ * Every call on one GPU uses that GPU's one scratch array, so calls that overlap in
+ * time on one GPU (other streams, other threads) race: serialise them, e.g. on one
+ * stream. Scratch contents left by the last call are never read by the next.
+ */
+#define AA_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+int aa_single_pulse_noalloc(aa_plan_t plan, const int32_t* d_dd, int64_t dd_pitch, int64_t dd_t0, int64_t dd_n,
+                            int64_t t_begin, int64_t t_end, int64_t t_total, aa_candidate_t* d_cand, int32_t cap,
+                            int32_t* d_count, float* d_best, int64_t best_pitch, void* stream);
+
 /* ---- per-range time decimation --------------------------------------------------
  * Beyond the paper, whose dedispersion phase (section 2.1) is brute force at the input
  * resolution. The trials are split into consecutive ranges; range r (first trial

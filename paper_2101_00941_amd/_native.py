@@ -128,6 +128,7 @@ def lib():
         "aa_batch_run": (C.c_int, [C.POINTER(BatchBeam), i32, i32, vp, sz, vp, i32, vp, C.c_uint32,
                                    C.POINTER(BatchInfo), vp]),
         "aa_single_pulse": (C.c_int, [vp, vp, i64, i64, i64, i64, i64, i64, vp, sz, vp, i32, vp, vp, i64, vp]),
+        "aa_single_pulse_noalloc": (C.c_int, [vp, vp, i64, i64, i64, i64, i64, i64, vp, i32, vp, vp, i64, vp]),
         "aa_decimate2": (C.c_int, [vp, i64, i64, i32, vp, i64, vp]),
         "aa_cluster": (C.c_int, [vp, i64, i32, i64, vp, i64, C.POINTER(i64)]),
         "aa_range_plan": (C.c_int, [C.POINTER(PlanDesc), C.POINTER(i32), C.POINTER(i32), i32, C.POINTER(vp)]),

@@ -183,6 +183,25 @@ class Plan:
                                         best.stride(0) if best is not None else 0, _stream_handle(stream)))
         return cand, count, best
 
+    def single_pulse_noalloc(self, dd, cand, count, dd_t0=0, dd_n=None, t_begin=0, t_end=None, t_total=None,
+                             cap=None, best=None, stream=None):
+        """aa_single_pulse_noalloc: the search with the library's fixed scratch (no work
+        buffer, nothing allocated by the call). cand, count (and best) are the caller's."""
+        import torch
+        if dd.dtype != torch.int32 or not dd.is_cuda or dd.dim() != 2 or dd.stride(1) != 1:
+            raise ValueError("dd must be an int32 CUDA tensor [ndm, pitch] with unit column stride")
+        dd_n = min(self.info["n_dd"] - dd_t0, dd.shape[1]) if dd_n is None else int(dd_n)
+        t_end = self.info["n_start"] if t_end is None else int(t_end)
+        t_total = self.info["n_start"] if t_total is None else int(t_total)
+        cap = cand.numel() // 24 if cap is None else int(cap)
+        if cand.dtype != torch.uint8 or cand.numel() < cap * 24:
+            raise ValueError("cand must be a uint8 buffer of at least cap * 24 bytes")
+        N.check(N.lib().aa_single_pulse_noalloc(self._h, _ptr(dd), dd.stride(0), int(dd_t0), dd_n, int(t_begin), t_end,
+                                                t_total, _ptr(cand), cap, _ptr(count),
+                                                _ptr(best) if best is not None else None,
+                                                best.stride(0) if best is not None else 0, _stream_handle(stream)))
+        return cand, count, best
+
 
 def decimate2(x, n_in=None, out=None, stream=None):
     """aa_decimate2: one rounding-average halving of every row of a uint8 CUDA tensor."""

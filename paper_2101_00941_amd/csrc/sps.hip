@@ -19,6 +19,9 @@
 // streamed search stalled on atomics combined with event waits.
 #pragma clang fp contract(off)
 
+#include <mutex>
+#include <string>
+
 #include "aa_internal.h"
 #include "numerics.h"
 #include "screen.h"
@@ -616,26 +619,88 @@ extern "C" int aa_single_pulse_work_bytes(aa_plan_t p, int64_t n_starts, size_t*
     return AA_OK;
 }
 
+namespace aa {
+namespace {
+// Argument checks shared by aa_single_pulse and aa_single_pulse_noalloc.
+int check_single_pulse(const char* fn, aa_plan_t p, const int32_t* d_dd, int64_t dd_pitch, int64_t dd_t0, int64_t dd_n,
+                       int64_t t_begin, int64_t t_end, int64_t t_total, aa_candidate_t* d_cand, int32_t cap,
+                       int32_t* d_count, float* d_best, int64_t best_pitch) {
+    const std::string f(fn);
+    if (!p || !d_dd || !d_count || (cap > 0 && !d_cand)) return fail(AA_EINVAL, f + ": null argument");
+    if (p->device < 0) return fail(AA_EINVAL, f + ": plan was created host-only");
+    if (p->nwidths > kMaxWidths) return fail(AA_EINVAL, f + ": more than 32 widths");
+    if (cap < 0) return fail(AA_EINVAL, f + ": cap < 0");
+    if (t_begin < 0 || t_end <= t_begin || t_begin % p->stat_block)
+        return fail(AA_EINVAL, f + ": need 0 <= t_begin < t_end and t_begin a multiple of stat_block");
+    if (t_total >= 0 && t_end > t_total) return fail(AA_EINVAL, f + ": t_end > t_total");
+    if (dd_n < 1 || dd_n > dd_pitch) return fail(AA_EINVAL, f + ": need 1 <= dd_n <= dd_pitch");
+    if (dd_t0 > (t_begin > 0 ? t_begin - 1 : t_begin)) return fail(AA_EINVAL, f + ": plane misses the left halo column");
+    const int64_t right = (t_total >= 0 && t_end >= t_total) ? t_end : t_end + 1;
+    if (dd_t0 + dd_n < right + p->wmax - 1) return fail(AA_EINVAL, f + ": plane too short for the right edge");
+    if (d_best && best_pitch < t_end - t_begin) return fail(AA_EINVAL, f + ": best_pitch too small");
+    return AA_OK;
+}
+
+// Scratch of aa_single_pulse_noalloc: one copy per GPU, alive until the process ends.
+// Host code never passes `scratch` itself to a kernel (in host code the name is only a
+// stand-in for the symbol): it passes the device address that hipGetSymbolAddress
+// returned for the current device.
+__device__ __align__(256) uint8_t scratch[AA_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[256] = {};
+
+// The device address of `scratch` on the current device, looked up once per device.
+int scratch_ptr(void** out) {
+    int dev = 0;
+    AA_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 256) return fail(AA_EINVAL, "aa_single_pulse_noalloc: device index out of range");
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return hip_fail(e, "aa_single_pulse_noalloc: hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return AA_OK;
+}
+}  // namespace
+}  // namespace aa
+
 extern "C" int aa_single_pulse(aa_plan_t p, const int32_t* d_dd, int64_t dd_pitch, int64_t dd_t0, int64_t dd_n,
                                int64_t t_begin, int64_t t_end, int64_t t_total, void* d_work, size_t work_bytes,
                                aa_candidate_t* d_cand, int32_t cap, int32_t* d_count, float* d_best,
                                int64_t best_pitch, void* stream) {
     using namespace aa;
-    if (!p || !d_dd || !d_work || !d_count || (cap > 0 && !d_cand))
-        return fail(AA_EINVAL, "aa_single_pulse: null argument");
-    if (p->device < 0) return fail(AA_EINVAL, "aa_single_pulse: plan was created host-only");
-    if (p->nwidths > kMaxWidths) return fail(AA_EINVAL, "aa_single_pulse: more than 32 widths");
-    if (cap < 0) return fail(AA_EINVAL, "aa_single_pulse: cap < 0");
-    if (t_begin < 0 || t_end <= t_begin || t_begin % p->stat_block)
-        return fail(AA_EINVAL, "aa_single_pulse: need 0 <= t_begin < t_end and t_begin a multiple of stat_block");
-    if (t_total >= 0 && t_end > t_total) return fail(AA_EINVAL, "aa_single_pulse: t_end > t_total");
-    if (dd_n < 1 || dd_n > dd_pitch) return fail(AA_EINVAL, "aa_single_pulse: need 1 <= dd_n <= dd_pitch");
-    if (dd_t0 > (t_begin > 0 ? t_begin - 1 : t_begin)) return fail(AA_EINVAL, "aa_single_pulse: plane misses the left halo column");
-    const int64_t right = (t_total >= 0 && t_end >= t_total) ? t_end : t_end + 1;
-    if (dd_t0 + dd_n < right + p->wmax - 1) return fail(AA_EINVAL, "aa_single_pulse: plane too short for the right edge");
+    if (!d_work) return fail(AA_EINVAL, "aa_single_pulse: null argument");
+    const int rc = check_single_pulse("aa_single_pulse", p, d_dd, dd_pitch, dd_t0, dd_n, t_begin, t_end, t_total, d_cand,
+                                      cap, d_count, d_best, best_pitch);
+    if (rc != AA_OK) return rc;
     if (work_bytes < sps_work_bytes(p, t_end - t_begin)) return fail(AA_EINVAL, "aa_single_pulse: work buffer too small");
-    if (d_best && best_pitch < t_end - t_begin) return fail(AA_EINVAL, "aa_single_pulse: best_pitch too small");
     if (reinterpret_cast<uintptr_t>(d_work) & 255) return fail(AA_EINVAL, "aa_single_pulse: d_work must be 256-byte aligned");
     return launch_single_pulse(p, d_dd, dd_pitch, dd_t0, dd_n, t_begin, t_end, t_total, d_work, d_cand, cap, d_count,
+                               d_best, best_pitch, static_cast<hipStream_t>(stream));
+}
+
+extern "C" int aa_single_pulse_noalloc(aa_plan_t p, const int32_t* d_dd, int64_t dd_pitch, int64_t dd_t0, int64_t dd_n,
+                                       int64_t t_begin, int64_t t_end, int64_t t_total, aa_candidate_t* d_cand,
+                                       int32_t cap, int32_t* d_count, float* d_best, int64_t best_pitch, void* stream) {
+    using namespace aa;
+    int rc = check_single_pulse("aa_single_pulse_noalloc", p, d_dd, dd_pitch, dd_t0, dd_n, t_begin, t_end, t_total,
+                                d_cand, cap, d_count, d_best, best_pitch);
+    if (rc != AA_OK) return rc;
+    const size_t need = sps_work_bytes(p, t_end - t_begin);
+    if (need > static_cast<size_t>(AA_NOALLOC_SCRATCH_BYTES))
+        return fail(AA_EINVAL, "aa_single_pulse_noalloc: the search needs " + std::to_string(need) +
+                                   " bytes of scratch, more than the fixed " +
+                                   std::to_string(static_cast<size_t>(AA_NOALLOC_SCRATCH_BYTES)) +
+                                   "; use aa_single_pulse with a work buffer or search fewer starts per call");
+    void* ptr = nullptr;
+    rc = scratch_ptr(&ptr);
+    if (rc != AA_OK) return rc;
+    // every scratch word the kernels read is written first in the same call (moments,
+    // norms, row counts cleared by the statistics kernel, every mask word by detection)
+    return launch_single_pulse(p, d_dd, dd_pitch, dd_t0, dd_n, t_begin, t_end, t_total, ptr, d_cand, cap, d_count,
                                d_best, best_pitch, static_cast<hipStream_t>(stream));
 }
