@@ -189,11 +189,12 @@ def stream_run(plan, src, nsamp, chunk, S, serial=False, sdma=False, staged=Fals
             assert c0 + n <= src_cols
             pipe.submit(b, src[:, c0:c0 + n], nsamp=n, pitch=pitch, tag=k, last=(s0 + n == nsamp))
             nk += 1
-        ncand, cands, bad = 0, [], 0
+        ncand, cands, bad, over = 0, [], 0, 0
         for _ in range(nk):
             r = pipe.poll(timeout_us=60_000_000)
             assert r is not None, "pipeline stalled"
             bad += r["status"] not in (0, -5)
+            over += r["status"] == -5
             ncand += r["n_true"]
             if want_cands:
                 cands.extend((int(c["dm_idx"]), int(c["t"]), int(c["width"]), float(c["snr"])) for c in r["cand"])
@@ -201,7 +202,7 @@ def stream_run(plan, src, nsamp, chunk, S, serial=False, sdma=False, staged=Fals
         st = pipe.stats()
         pipe.close()
         assert bad == 0, "a chunk failed"
-        out = dict(wall_ms=wall * 1e3, candidates=ncand, **st)
+        out = dict(wall_ms=wall * 1e3, candidates=ncand, overflowed_chunks=over, **st)
         if want_cands:
             out["cand_list"] = sorted(cands, key=lambda c: (c[0], c[1]))
     out["hidden_frac"] = out["overlap_ms"] / out["copy_ms"] if out["copy_ms"] > 0 else None
@@ -294,6 +295,8 @@ def streamed_compact(variant, budget_gb, cap, survey_host=None, resident_cands=N
         chunk, nchunks = 1 << 18, 16
         log(f"[bench] streamed survey plan, {nchunks} chunks of {chunk}")
         modes = [("plain", 1, True, False, False, False)] + [("streams", s, False, False, False, False) for s in (2, 4)]
+        # a strong pulse gives tens of thousands of candidates in one sub-chunk
+        cap = max(cap, 1 << 18)
         rows = _stream_rows(plan, survey_host, nchunks * chunk, chunk, modes, budget, cap, src_cols=ws["nsamp"])
         res = _compact_rows(rows, chunks=nchunks)
         if resident_cands is not None:
@@ -304,7 +307,7 @@ def streamed_compact(variant, budget_gb, cap, survey_host=None, resident_cands=N
                            want_cands=True)
             got = [c for c in r["cand_list"] if c[1] < e]
             want = [c for c in resident_cands if c[1] < e]
-            res["check"] = {"starts": e, "candidates": len(want),
+            res["check"] = {"starts": e, "candidates": len(want), "overflowed_chunks": r["overflowed_chunks"],
                             "identical_to_resident": [c[:3] for c in got] == [c[:3] for c in want]
                             and all(abs(g[3] - h[3]) <= 1e-5 * max(1.0, abs(h[3])) for g, h in zip(got, want))}
             log(f"[bench] streamed survey vs resident over starts < {e}: {res['check']}")
@@ -314,7 +317,7 @@ def streamed_compact(variant, budget_gb, cap, survey_host=None, resident_cands=N
 
 def _compact_rows(rows, chunks):
     keep = ("wall_ms", "speedup_vs_plain", "hidden_frac", "efficiency", "copy_ms", "kernel_ms", "overlap_ms",
-            "span_ms", "dm_trial_samples_per_s")
+            "span_ms", "dm_trial_samples_per_s", "overflowed_chunks")
     out = {"chunks": chunks}
     for r in rows:
         key = r["mode"] if r["mode"] == "plain" else f"S{r['nstreams']}"
