@@ -163,7 +163,7 @@ def h2d_probe(torch, nchan, ncols, pitch):
 
 
 def stream_run(plan, src, nsamp, chunk, S, serial=False, sdma=False, staged=False, budget=16 << 30, cap=1 << 14,
-               src_cols=None, reps=2, want_cands=False):
+               src_cols=None, reps=2, want_cands=False, min_piece_work=0):
     """One beam streamed through a pipeline: `nsamp` samples in chunks of `chunk`, read
     from `src` (uint8 [nchan, >= src_cols], pinned torch tensor or pageable numpy array).
     With src_cols < nsamp the source columns repeat: chunk k reads columns
@@ -178,7 +178,7 @@ def stream_run(plan, src, nsamp, chunk, S, serial=False, sdma=False, staged=Fals
     out = None
     for _ in range(reps):
         pipe = Pipeline(nstreams=S, max_beams=1, max_chunk=chunk, cand_cap=cap, hbm_budget=budget, serial=serial,
-                        timing=True, sdma_copy=sdma, staged=staged)
+                        timing=True, sdma_copy=sdma, staged=staged, min_piece_work=min_piece_work)
         b = pipe.add_beam(plan)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -210,11 +210,12 @@ def stream_run(plan, src, nsamp, chunk, S, serial=False, sdma=False, staged=Fals
     return out
 
 
-def _stream_rows(plan, host, nsamp, chunk, modes, budget, cap, src_cols=None, pageable=None):
+def _stream_rows(plan, host, nsamp, chunk, modes, budget, cap, src_cols=None, pageable=None, min_piece_work=0):
     rows = []
     for mode, S, serial, sdma, is_pageable, staged in modes:
         src = pageable if is_pageable else host
-        r = stream_run(plan, src, nsamp, chunk, S, serial, sdma, staged, budget, cap, src_cols)
+        r = stream_run(plan, src, nsamp, chunk, S, serial, sdma, staged, budget, cap, src_cols,
+                       min_piece_work=min_piece_work)
         r.update(mode=mode, nstreams=S)
         r["dm_trial_samples_per_s"] = plan.info["ndm"] * (nsamp - plan.info["maxshift"]) / (r["wall_ms"] * 1e-3)
         rows.append(r)
@@ -257,9 +258,12 @@ def streamed(a):
     pageable = np.array(host.numpy(), copy=True)
     # (name, compute streams, serial, runtime copies, pageable input, staged)
     modes = ([("pageable-default", 1, True, False, True, False), ("plain", 1, True, False, False, False)]
-             + [("streams", s, False, False, False, False) for s in (1, 2, 4, 8)]
+             + [("streams", s, False, False, False, False) for s in a.streams]
              + [("streams-sdma", 2, False, True, False, False), ("pageable-staged", 4, False, False, True, True)])
-    rows = _stream_rows(plan, host, nsamp, chunk, modes, budget, a.stream_cap, pageable=pageable)
+    if a.only_streams:
+        modes = [m for m in modes if m[0] in ("plain", "streams")]
+    rows = _stream_rows(plan, host, nsamp, chunk, modes, budget, a.stream_cap, pageable=pageable,
+                        min_piece_work=a.min_piece_work)
     return dict(workload=w["name"], chunk=chunk, ndm=plan.info["ndm"], nchan=nchan, nsamp=nsamp,
                 dedisp_variant=plan.variant, h2d_probe=probe,
                 hw_queues=os.environ.get("GPU_MAX_HW_QUEUES", "default"), runs=rows)
@@ -470,7 +474,11 @@ def main():
                     help="dedispersion kernel variant, or 'auto' (resident and batched modes: the autotuner; "
                          "streamed and serving modes: the plan default)")
     ap.add_argument("--ndm", type=int, default=0, help="use only the first NDM trials (profiling runs)")
-    ap.add_argument("--mode", default="resident", choices=["resident", "streamed", "serving", "batched"])
+    ap.add_argument("--mode", default="resident", choices=["resident", "streamed", "serving", "batched", "decimated"])
+    ap.add_argument("--streams", type=int, nargs="+", default=[1, 2, 4, 8], help="streamed mode: stream counts")
+    ap.add_argument("--only-streams", action="store_true", help="streamed mode: plain and --streams runs only")
+    ap.add_argument("--min-piece-work", type=int, default=0,
+                    help="streamed mode: smallest sub-chunk (0: the library default 2^33, -1: always split)")
     ap.add_argument("--beams", type=int, default=32)
     ap.add_argument("--serve-seconds", type=float, default=20.0)
     ap.add_argument("--serve-streams", type=int, default=4)
@@ -507,6 +515,19 @@ def main():
         if a.budget_gb == 16.0:
             a.budget_gb = 200.0
         print(json.dumps(serving(a)), flush=True)
+        return
+    if a.mode == "decimated":
+        import torch
+
+        from synth.workloads import make_input, workload
+        w = workload("survey_4096ch_1M")
+        pitch = (w["nsamp"] + 255) // 256 * 256
+        x_host = torch.empty((w["nchan"], pitch), dtype=torch.uint8).pin_memory()
+        make_input(w, pitch=pitch, out=x_host.numpy())
+        torch.cuda.set_device(0)
+        x = x_host.to("cuda:0")
+        v = 20 if a.variant == "auto" else int(a.variant)
+        print(json.dumps(decimated_run(w, x, v, torch.cuda.current_stream(), steps=a.steps)), flush=True)
         return
 
     import torch
