@@ -681,9 +681,12 @@ def decimated_run(w, x, variant, stream, steps=5):
     (steps 1/16 .. 2) at factors 1, 2, 4, .. 32, one aa_range_run per step (decimation,
     dedispersion and search of every range). Reports ms per run (HIP events on the
     launch stream), the input-sample rate and the adds it performs."""
+    import ctypes as C
+
     import torch
 
     from paper_2101_00941_amd import RangePlan
+    from paper_2101_00941_amd import _native as N
     first, factor = SURVEY_RANGES
     rp = RangePlan(w["nchan"], w["nsamp"], w["f_top"], w["foff"], w["tsamp"], w["dms"], w["widths"], w["threshold"],
                    first, factor, w["stat_block"])
@@ -702,13 +705,16 @@ def decimated_run(w, x, variant, stream, steps=5):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     ndm = len(w["dms"])
-    adds = 0
-    for r, f in enumerate(factor):
-        hi = first[r + 1] if r + 1 < len(first) else ndm
-        adds += (hi - first[r]) * (w["nsamp"] // f) * w["nchan"]
+    from paper_2101_00941_amd import Plan
+    n_dd_plain = Plan.from_workload(w, host_only=True).info["n_dd"]
+    adds = 0   # algorithmic: trials x N_dd x channels of every range, N_dd at its resolution
+    for r in range(len(first)):
+        info = N.PlanInfo()
+        N.check(N.lib().aa_plan_info(rp.range_plan(r)[0], C.byref(info)))
+        adds += info.ndm * info.n_dd * info.nchan
     out = {"ranges_first": first, "factors": factor, "ms_per_run": ms, "candidates": int(count.item()),
            "input_samples_per_s": ndm * w["nsamp"] / (ms * 1e-3), "adds_per_run": adds,
-           "adds_vs_plain": adds / (ndm * w["nsamp"] * w["nchan"]), "dedisp_variant": variant}
+           "adds_vs_plain": adds / (ndm * n_dd_plain * w["nchan"]), "dedisp_variant": variant}
     log(f"[bench] decimated ranges: {ms:.2f} ms per run, {out['candidates']} candidates, "
         f"{out['adds_vs_plain']:.3f} of the plain adds")
     del work, cand, count, rp
