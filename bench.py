@@ -531,7 +531,7 @@ def main():
         make_input(w, pitch=pitch, out=x_host.numpy())
         torch.cuda.set_device(0)
         x = x_host.to("cuda:0")
-        v = 20 if a.variant == "auto" else int(a.variant)
+        v = None if a.variant == "auto" else int(a.variant)
         print(json.dumps(decimated_run(w, x, v, torch.cuda.current_stream(), steps=a.steps)), flush=True)
         return
 
@@ -657,7 +657,7 @@ def main():
                                     "unit": "TOP/s", "frac": ach / ALU_PEAK_TOPS, "bound": "alu",
                                     "value_if_used": ndm * n_dd / ((m + ms_sps) * 1e-3)}
     if not a.no_extras and not a.ndm and w["name"] == "survey_4096ch_1M":
-        res["decimated"] = decimated_run(w, x, plan.variant, stream)
+        res["decimated"] = decimated_run(w, x, None, stream)
     if not a.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         res["cpu_baseline"] = cpu_baseline(w, x_np[:, :w["nsamp"]])
@@ -679,8 +679,9 @@ SURVEY_RANGES = ([0, 512, 1024, 1536, 2048, 2432], [1, 2, 4, 8, 16, 32])
 def decimated_run(w, x, variant, stream, steps=5):
     """Per-range time decimation on the resident survey input: the plan's six DM ranges
     (steps 1/16 .. 2) at factors 1, 2, 4, .. 32, one aa_range_run per step (decimation,
-    dedispersion and search of every range). Reports ms per run (HIP events on the
-    launch stream), the input-sample rate and the adds it performs."""
+    dedispersion and search of every range). variant None autotunes each range on its
+    own decimated input. Reports ms per run (HIP events on the launch stream), the
+    input-sample rate and the adds it performs."""
     import ctypes as C
 
     import torch
@@ -690,7 +691,12 @@ def decimated_run(w, x, variant, stream, steps=5):
     first, factor = SURVEY_RANGES
     rp = RangePlan(w["nchan"], w["nsamp"], w["f_top"], w["foff"], w["tsamp"], w["dms"], w["widths"], w["threshold"],
                    first, factor, w["stat_block"])
-    rp.set_variant(variant)
+    if variant is None:
+        tuned = rp.autotune(x, n_in=w["nsamp"], reps=1)
+        log(f"[bench] decimated ranges: autotuned variants {tuned}")
+    else:
+        rp.set_variant(variant)
+        tuned = [variant] * len(first)
     cap = 1 << 20
     work = torch.empty(rp.work_bytes(w["nsamp"], cap), dtype=torch.uint8, device=x.device)
     cand = torch.empty(cap * 24, dtype=torch.uint8, device=x.device)
@@ -714,7 +720,7 @@ def decimated_run(w, x, variant, stream, steps=5):
         adds += info.ndm * info.n_dd * info.nchan
     out = {"ranges_first": first, "factors": factor, "ms_per_run": ms, "candidates": int(count.item()),
            "input_samples_per_s": ndm * w["nsamp"] / (ms * 1e-3), "adds_per_run": adds,
-           "adds_vs_plain": adds / (ndm * n_dd_plain * w["nchan"]), "dedisp_variant": variant}
+           "adds_vs_plain": adds / (ndm * n_dd_plain * w["nchan"]), "dedisp_variants": tuned}
     log(f"[bench] decimated ranges: {ms:.2f} ms per run, {out['candidates']} candidates, "
         f"{out['adds_vs_plain']:.3f} of the plain adds")
     del work, cand, count, rp

@@ -250,6 +250,10 @@ int aa_single_pulse_noalloc(aa_plan_t plan, const int32_t* d_dd, int64_t dd_pitc
  *   aa_range_run       all ranges over d_in (uint8 [nchan][in_pitch], n_in samples) on
  *                      `stream`: *d_count receives the true total, d_cand the first cap
  *                      candidates. AA_ESHORT if a range is too short at n_in.
+ *   aa_range_autotune  decimates d_in into d_work and runs aa_autotune on each range's plan
+ *                      with its own decimated input (reps runs per variant), so each range
+ *                      gets its fastest variant; ms_out, if not null, receives
+ *                      [nranges][aa_variant_count()] mean times. Synchronises `stream`.
  */
 typedef struct aa_range_plan_s* aa_range_plan_t;
 
@@ -261,6 +265,8 @@ int aa_range_plan_get(aa_range_plan_t rp, int32_t r, aa_plan_t* plan, int32_t* f
 int aa_range_work_bytes(aa_range_plan_t rp, int64_t n_in, int32_t cap, size_t* out);
 int aa_range_run(aa_range_plan_t rp, const uint8_t* d_in, int64_t in_pitch, int64_t n_in, void* d_work,
                  size_t work_bytes, aa_candidate_t* d_cand, int32_t cap, int32_t* d_count, void* stream);
+int aa_range_autotune(aa_range_plan_t rp, const uint8_t* d_in, int64_t in_pitch, int64_t n_in, void* d_work,
+                      size_t work_bytes, int32_t reps, void* stream, float* ms_out);
 void aa_range_plan_destroy(aa_range_plan_t rp);
 
 /* ---- cross-DM candidate clustering (host) -------------------------------------

@@ -135,6 +135,7 @@ def lib():
         "aa_range_plan_get": (C.c_int, [vp, i32, C.POINTER(vp), C.POINTER(i32), C.POINTER(i32)]),
         "aa_range_work_bytes": (C.c_int, [vp, i64, i32, C.POINTER(sz)]),
         "aa_range_run": (C.c_int, [vp, vp, i64, i64, vp, sz, vp, i32, vp, vp]),
+        "aa_range_autotune": (C.c_int, [vp, vp, i64, i64, vp, sz, i32, vp, C.POINTER(C.c_float)]),
         "aa_range_plan_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():

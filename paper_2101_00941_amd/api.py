@@ -257,6 +257,26 @@ class RangePlan:
         N.check(N.lib().aa_range_work_bytes(self._h, int(n_in), int(cap), C.byref(v)))
         return v.value
 
+    def autotune(self, x, n_in=None, reps=1, work=None, stream=None):
+        """aa_range_autotune: each range's fastest variant on its own decimated input.
+        Returns the chosen variant per range."""
+        import torch
+        n_in = x.shape[1] if n_in is None else int(n_in)
+        wb = self.work_bytes(n_in, 0)
+        if work is None or work.numel() < wb:
+            work = torch.empty(wb, dtype=torch.uint8, device=x.device)
+        nv = N.lib().aa_variant_count()
+        ms = (C.c_float * (nv * len(self.first)))()
+        N.check(N.lib().aa_range_autotune(self._h, _ptr(x), x.stride(0), n_in, _ptr(work), work.numel(), int(reps),
+                                          _stream_handle(stream), ms))
+        self.tune_ms = [[float(ms[r * nv + v]) for v in range(nv)] for r in range(len(self.first))]
+        out = []
+        for r in range(len(self.first)):
+            v = C.c_int32()
+            N.check(N.lib().aa_plan_get_variant(self.range_plan(r)[0], C.byref(v)))
+            out.append(v.value)
+        return out
+
     def run(self, x, n_in=None, cap=1 << 16, work=None, cand=None, count=None, stream=None):
         """aa_range_run. Returns (cand uint8 [cap*24] tensor, count int32 [1] tensor)."""
         import torch

@@ -244,29 +244,69 @@ extern "C" int aa_range_work_bytes(aa_range_plan_t rp, int64_t n_in, int32_t cap
     return AA_OK;
 }
 
-extern "C" int aa_range_run(aa_range_plan_t rp, const uint8_t* d_in, int64_t in_pitch, int64_t n_in, void* d_work,
-                            size_t work_bytes, aa_candidate_t* d_cand, int32_t cap, int32_t* d_count, void* stream_) {
-    if (!rp || !d_in || !d_work || !d_count || cap < 0 || (cap > 0 && !d_cand))
-        return fail(AA_EINVAL, "aa_range_run: null argument");
-    if ((reinterpret_cast<uintptr_t>(d_in) & 15) || (in_pitch & 15) || n_in > in_pitch || n_in < 2)
-        return fail(AA_EINVAL, "aa_range_run: d_in and in_pitch must be multiples of 16 with 2 <= n_in <= in_pitch");
-    if (reinterpret_cast<uintptr_t>(d_work) & 255) return fail(AA_EINVAL, "aa_range_run: d_work must be 256-byte aligned");
-    for (aa_plan_t p : rp->plans)
-        if (p->device < 0) return fail(AA_EINVAL, "aa_range_run: plan was created host-only");
-    RangeLayout L;
-    int rc = range_layout(rp, n_in, cap, &L);
-    if (rc != AA_OK) return rc;
-    if (work_bytes < L.total) return fail(AA_EINVAL, "aa_range_run: work buffer too small (aa_range_work_bytes)");
-    hipStream_t stream = static_cast<hipStream_t>(stream_);
-    uint8_t* W = static_cast<uint8_t*>(d_work);
-    // decimation levels 1 .. kmax, each from the one before
+namespace {
+// Decimation levels 1 .. kmax into the work buffer, each from the one before.
+int decimate_levels(const aa_range_plan_s* rp, const RangeLayout& L, const uint8_t* d_in, int64_t in_pitch, uint8_t* W,
+                    hipStream_t stream) {
     const int kmax = static_cast<int>(L.level_off.size()) - 1;
     for (int k = 1; k <= kmax; ++k) {
         const uint8_t* src = k == 1 ? d_in : W + L.level_off[k - 1];
         const int64_t sp = k == 1 ? in_pitch : L.level_pitch[k - 1];
-        rc = launch_halve(src, sp, L.level_n[k - 1], rp->nchan, W + L.level_off[k], L.level_pitch[k], stream);
+        const int rc = launch_halve(src, sp, L.level_n[k - 1], rp->nchan, W + L.level_off[k], L.level_pitch[k], stream);
         if (rc != AA_OK) return rc;
     }
+    return AA_OK;
+}
+
+int check_run_args(const aa_range_plan_s* rp, const uint8_t* d_in, int64_t in_pitch, int64_t n_in, const void* d_work) {
+    if (!rp || !d_in || !d_work) return fail(AA_EINVAL, "aa_range: null argument");
+    if ((reinterpret_cast<uintptr_t>(d_in) & 15) || (in_pitch & 15) || n_in > in_pitch || n_in < 2)
+        return fail(AA_EINVAL, "aa_range: d_in and in_pitch must be multiples of 16 with 2 <= n_in <= in_pitch");
+    if (reinterpret_cast<uintptr_t>(d_work) & 255) return fail(AA_EINVAL, "aa_range: d_work must be 256-byte aligned");
+    for (aa_plan_t p : rp->plans)
+        if (p->device < 0) return fail(AA_EINVAL, "aa_range: plan was created host-only");
+    return AA_OK;
+}
+}  // namespace
+
+extern "C" int aa_range_autotune(aa_range_plan_t rp, const uint8_t* d_in, int64_t in_pitch, int64_t n_in, void* d_work,
+                                 size_t work_bytes, int32_t reps, void* stream_, float* ms_out) {
+    int rc = check_run_args(rp, d_in, in_pitch, n_in, d_work);
+    if (rc != AA_OK) return rc;
+    RangeLayout L;
+    rc = range_layout(rp, n_in, 0, &L);
+    if (rc != AA_OK) return rc;
+    if (work_bytes < L.total) return fail(AA_EINVAL, "aa_range_autotune: work buffer too small (aa_range_work_bytes)");
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    uint8_t* W = static_cast<uint8_t*>(d_work);
+    rc = decimate_levels(rp, L, d_in, in_pitch, W, stream);
+    if (rc != AA_OK) return rc;
+    for (int r = 0; r < rp->nranges; ++r) {
+        aa_plan_s* p = rp->plans[r];
+        const int k = log2i(rp->factor[r]);
+        const int64_t n = L.level_n[k];
+        const int64_t op = (n - p->maxshift + 63) / 64 * 64;
+        rc = aa_autotune(p, k == 0 ? d_in : W + L.level_off[k], k == 0 ? in_pitch : L.level_pitch[k], n,
+                         reinterpret_cast<int32_t*>(W + L.plane), op, reps, stream_,
+                         ms_out ? ms_out + static_cast<int64_t>(r) * kNumDedispVariants : nullptr);
+        if (rc != AA_OK) return rc;
+    }
+    return AA_OK;
+}
+
+extern "C" int aa_range_run(aa_range_plan_t rp, const uint8_t* d_in, int64_t in_pitch, int64_t n_in, void* d_work,
+                            size_t work_bytes, aa_candidate_t* d_cand, int32_t cap, int32_t* d_count, void* stream_) {
+    if (!d_count || cap < 0 || (cap > 0 && !d_cand)) return fail(AA_EINVAL, "aa_range_run: null argument");
+    int rc = check_run_args(rp, d_in, in_pitch, n_in, d_work);
+    if (rc != AA_OK) return rc;
+    RangeLayout L;
+    rc = range_layout(rp, n_in, cap, &L);
+    if (rc != AA_OK) return rc;
+    if (work_bytes < L.total) return fail(AA_EINVAL, "aa_range_run: work buffer too small (aa_range_work_bytes)");
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    uint8_t* W = static_cast<uint8_t*>(d_work);
+    rc = decimate_levels(rp, L, d_in, in_pitch, W, stream);
+    if (rc != AA_OK) return rc;
     const int32_t stage_cap = std::max(cap, 1);
     aa_candidate_t* stage = reinterpret_cast<aa_candidate_t*>(W + L.stage);
     int32_t* counts = reinterpret_cast<int32_t*>(W + L.counts);

@@ -8,7 +8,7 @@ oracle checks sampled outputs, each computed on its own:
     samples and at a random one, and full 32768-sample runs of a few trials, for
     the autotuned variant, every matrix-core variant and one variant of each other
     kernel family;
-  * candidates: every 100th trial and the two trials on each side of every
+  * candidates (plain and per-range decimated): every 100th trial and the two trials on each side of every
     injected pulse's DM (127 rows, chosen from the signal model), over the full
     time range. The oracle dedisperses each of those rows and its neighbours over
     all samples (220 rows, threaded over the host cores) and runs its own search.
@@ -176,3 +176,77 @@ def test_survey_candidates_full_time(survey):
         found += any(abs(c[0] - r) <= 2 and abs(c[1] - p.t0) <= 512 for c in want)
     say(f"  {found} of {len(w['pulses'])} injected pulses found")
     assert found >= len(w["pulses"]) - 2
+
+
+def test_survey_decimated_ranges_rows(survey):
+    """Per-range time decimation at the survey size, as the bench runs it (six ranges at
+    factors 1..32, the autotuned variant): the GPU candidates of every 100th trial and of the
+    trials around each injected pulse equal the oracle's, which decimates the input itself
+    (channel blocks of 256, exact halvings), dedisperses those trials and their in-range
+    neighbours over the full decimated time range, and searches them per range."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+
+    import torch
+    from paper_2101_00941_amd import RangePlan, candidates_as_tuples, candidates_to_numpy
+    sv = survey
+    w, x, x_np = sv["w"], sv["x"], sv["x_np"]
+    first, factor = [0, 512, 1024, 1536, 2048, 2432], [1, 2, 4, 8, 16, 32]
+    ndm, nsamp, B = len(w["dms"]), w["nsamp"], w["stat_block"]
+    rp = RangePlan(w["nchan"], nsamp, w["f_top"], w["foff"], w["tsamp"], w["dms"], w["widths"], w["threshold"],
+                   first, factor, B)
+    rp.set_variant(sv["plan"].variant)
+    cap = 1 << 20
+    cand, count = rp.run(x, n_in=nsamp, cap=cap)
+    torch.cuda.synchronize()
+    got = candidates_as_tuples(candidates_to_numpy(cand, count))
+    assert 0 < len(got) < cap
+    say(f"  decimated: {len(got)} GPU candidates (variant {sv['plan'].variant})")
+    plans = oracle.range_plans(w["dms"], w["nchan"], nsamp, w["f_top"], w["foff"], w["tsamp"], w["widths"], B,
+                               first, factor)
+    # decimated inputs, level by level, in channel blocks (bounded temporaries)
+    levels = {1: x_np}
+    f = 1
+    while f < factor[-1]:
+        src = levels[f]
+        dst = np.empty((src.shape[0], src.shape[1] // 2), dtype=np.uint8)
+        for c0 in range(0, src.shape[0], 256):
+            dst[c0:c0 + 256] = oracle.decimate2(src[c0:c0 + 256])
+        f *= 2
+        levels[f] = dst
+    checked = set(_checked_rows(w, ndm))
+    want, rows_all = [], set()
+    jobs = []
+    for rp_o in plans:
+        lo, hi = rp_o["lo"], rp_o["hi"]
+        rows = sorted(r - lo for r in checked if lo <= r < hi)
+        if not rows:
+            continue
+        rows_all |= {lo + r for r in rows}
+        need = sorted({q for r in rows for q in (r - 1, r, r + 1) if 0 <= q < hi - lo})
+        jobs.append((rp_o, rows, need))
+    say(f"  oracle: {len(rows_all)} checked trials over {len(jobs)} ranges")
+
+    def one(args):
+        rp_o, q = args
+        M = rp_o["sizes"]["maxshift"]
+        return rp_o["lo"], q, oracle.dedisperse_rows(levels[rp_o["f"]], rp_o["shifts"], [q], rp_o["n"], M)[0]
+
+    work = [(rp_o, q) for rp_o, rows, need in jobs for q in need]
+    D = {}
+    with ThreadPoolExecutor(max(1, min(16, os.cpu_count() or 1))) as pool:
+        for lo, q, row in pool.map(one, work):
+            D[(lo, q)] = row
+    for rp_o, rows, need in jobs:
+        lo, f, T = rp_o["lo"], rp_o["f"], rp_o["sizes"]["n_start"]
+        for a, b in _runs(rows):
+            r0, r1 = max(a - 1, 0), min(b + 1, rp_o["hi"] - lo - 1)
+            plane = np.stack([D[(lo, q)] for q in range(r0, r1 + 1)])
+            c, _ = oracle.single_pulse(plane, 0, 0, T, T, w["widths"], w["threshold"], rp_o["block"], row0=r0,
+                                       ndm=rp_o["hi"] - lo, report_rows=list(range(a, b + 1)))
+            want.extend((lo + d, f * t, f * wd, s) for d, t, wd, s in c)
+    want.sort(key=lambda c: (c[0], c[1]))
+    have = [c for c in got if c[0] in rows_all]
+    say(f"  {len(want)} oracle candidates on the checked trials, {len(have)} GPU")
+    assert len(want) > 0
+    assert_candidates_equal(have, want)

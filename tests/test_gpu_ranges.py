@@ -88,3 +88,19 @@ def test_range_plan_errors(case):
         RangePlan(*args, [0, 200], [1, 3])             # not a power of two
     with pytest.raises(AAError):
         RangePlan(*args, [0, 700], [1, 2])             # first trial past ndm
+
+
+def test_range_autotune_picks_per_range_and_matches_oracle(case):
+    import torch
+    from paper_2101_00941_amd import RangePlan, candidates_as_tuples, candidates_to_numpy
+    c = case
+    rp = RangePlan(c["nchan"], c["nsamp"], F_TOP, c["foff"], TSAMP, c["dms"], WIDTHS, 6.0, c["first"], c["factor"], 8192)
+    xd = to_device(c["x"], c["nsamp"])
+    chosen = rp.autotune(xd, n_in=c["nsamp"], reps=1)
+    say(f"range autotune: {chosen}")
+    for r, v in enumerate(chosen):
+        timed = [(m, k) for k, m in enumerate(rp.tune_ms[r]) if m >= 0]
+        assert v == min(timed)[1]
+    cand, count = rp.run(xd, n_in=c["nsamp"], cap=1 << 14)
+    torch.cuda.synchronize()
+    assert_candidates_equal(candidates_as_tuples(candidates_to_numpy(cand, count)), c["want"]["candidates"])
