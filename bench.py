@@ -371,6 +371,7 @@ def serving(a):
             ids = [pipe.add_beam(p) for p in plans]
             nxt = [0] * len(beams)
             lat, work, done = [], 0, 0
+            results = {}                     # tag -> (status, t range, candidate list)
             t0 = time.perf_counter()
 
             def drain(timeout):
@@ -381,6 +382,7 @@ def serving(a):
                     lat.append(r["latency_s"])
                     work += plans[r["beam"]].info["ndm"] * (r["t_end"] - r["t_begin"])
                     done += 1
+                    results[r["tag"]] = (r["status"], r["t_begin"], r["t_end"], r["n_true"], r["cand"].tobytes())
                     r = pipe.poll(timeout_us=0)
 
             for i, (ta, b) in enumerate(arrivals):
@@ -401,6 +403,13 @@ def serving(a):
                        p99_ms=float(np.percentile(lat_ms, 99)), mean_ms=float(lat_ms.mean()),
                        dm_trial_samples_per_s=work / wall, arena_peak_gb=st["arena_peak"] / 2**30)
             out[f"x{scale:g}_{mode}"] = res
+            if mode == "continuous":
+                first_results = results
+            else:
+                # every chunk's result in the mix equals the one-at-a-time (plain) result
+                same = results.keys() == first_results.keys() and all(results[k] == first_results[k] for k in results)
+                out[f"x{scale:g}_identical"] = bool(same)
+                log(f"[bench] serving x{scale:g}: continuous and plain results identical: {same}")
             log(f"[bench] serving x{scale:g} {mode}: {len(arrivals)} chunks, p50 {res['p50_ms']:.1f} ms, "
                 f"p99 {res['p99_ms']:.1f} ms, {res['dm_trial_samples_per_s']:.3e} DM-trial*samples/s, "
                 f"arena peak {res['arena_peak_gb']:.1f} GB")
@@ -743,6 +752,9 @@ def serving_compact(a, variant):
     out = {"beams": full["beams"], "seconds": full["seconds"], "streams": full["streams"],
            "hbm_budget_gb": full["hbm_budget_gb"], "dedisp_variant": full["dedisp_variant"]}
     for k, r in full["results"].items():
+        if isinstance(r, bool):
+            out[k] = r
+            continue
         out[k] = {q: round(r[q], 4) for q in ("p50_ms", "p99_ms", "mean_ms", "dm_trial_samples_per_s")}
         out[k]["chunks"] = r["chunks"]
     return out
