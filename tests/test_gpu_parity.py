@@ -208,3 +208,28 @@ def test_single_pulse_argument_errors():
         p.single_pulse(D, dd_t0=1024, dd_n=4000, t_begin=1024, t_end=2048, t_total=-1)  # no left halo
     with pytest.raises(AAError):
         p.single_pulse(D, dd_n=2000, t_begin=0, t_end=2048, t_total=-1)  # no right edge columns
+
+
+@pytest.mark.parametrize("nchan,widths,thr", [
+    # 32 widths (the most a plan may hold), consecutive
+    (96, list(range(1, 33)), 4.0),
+    # the widest boxcar (1024) with window sums that can pass 2^31: the launcher then
+    # evaluates every cell in float64 instead of the integer screen
+    (8300, [1, 16, 256, 1024], 3.0),
+])
+def test_extreme_widths_match_oracle(nchan, widths, thr):
+    from paper_2101_00941_amd import Plan
+    nsamp = 9000
+    dms = [0.0, 0.5, 1.0, 1.5, 2.0]
+    x = make_filterbank(nchan, nsamp, 1500.0, 0.0625, 64e-6, [Pulse(1.0, 4000.0, 300.0, 3.0)], seed=nchan)
+    want = oracle.run(x, nsamp, 1500.0, 0.0625, 64e-6, dms, widths, thr, stat_block=2048, want_best=True)
+    p = Plan(nchan, nsamp, 1500.0, 0.0625, 64e-6, dms, widths, thr, 2048)
+    say(f"extreme widths nchan {nchan} widths {widths[:4]}..{widths[-1]} ({len(widths)}), "
+        f"sums up to {nchan * 255 * widths[-1]:.3g}")
+    for with_best in (True, False):
+        r = run_gpu(p, x, nsamp, want_best=with_best, cap=1 << 16)
+        assert np.array_equal(r["D"], want["D"])
+        assert_candidates_equal(r["candidates"], want["candidates"])
+        if with_best:
+            assert np.array_equal(r["best"], want["best"])
+    assert len(want["candidates"]) > 0
