@@ -25,11 +25,11 @@ Modules:
 
 from .plan import K_DM, channel_freqs, shift_table, sizes
 from .dedisp import dedisperse, dedisperse_rows
-from .sps import block_moments, block_norms, best_plane, candidates, clipped_moments, single_pulse
+from .sps import block_moments, block_norms, best_plane, boxcar_strides, candidates, clipped_moments, single_pulse
 from .pipeline import run, run_chunked
 from .decimate import decimate, decimate2, range_plans, run_ranges
 from .cluster import cluster
 
 __all__ = ["K_DM", "channel_freqs", "shift_table", "sizes", "dedisperse", "dedisperse_rows",
-           "block_moments", "block_norms", "best_plane", "candidates", "clipped_moments", "single_pulse",
+           "block_moments", "block_norms", "best_plane", "boxcar_strides", "candidates", "clipped_moments", "single_pulse",
            "run", "run_chunked", "decimate", "decimate2", "range_plans", "run_ranges", "cluster"]

@@ -18,19 +18,19 @@ from .sps import single_pulse
 
 
 def run(x, nsamp, f_top, foff, tsamp, dms, widths, threshold, stat_block=32768, want_best=False, clip_sigma=0.0,
-        clip_iters=0):
+        clip_iters=0, boxcar_full_width=0):
     """Dedisperse all trials, then run the single-pulse search over every start."""
     s = shift_table(dms, x.shape[0], f_top, foff, tsamp)
     sz = sizes(s, nsamp, widths, stat_block)
     D = dedisperse(x, s, nsamp, sz["maxshift"])
     T = sz["n_start"]
     cands, best = single_pulse(D, 0, 0, T, T, widths, threshold, stat_block, want_best=want_best,
-                               clip_sigma=clip_sigma, clip_iters=clip_iters)
+                               clip_sigma=clip_sigma, clip_iters=clip_iters, boxcar_full_width=boxcar_full_width)
     return dict(shifts=s, sizes=sz, D=D, candidates=cands, best=best)
 
 
 def run_chunked(x, nsamp, f_top, foff, tsamp, dms, widths, threshold, chunk, stat_block=32768, clip_sigma=0.0,
-                clip_iters=0):
+                clip_iters=0, boxcar_full_width=0):
     """Same result as `run`, computed one chunk of `chunk` starts at a time."""
     if chunk % stat_block:
         raise ValueError("chunk must be a multiple of the stat block")
@@ -44,7 +44,7 @@ def run_chunked(x, nsamp, f_top, foff, tsamp, dms, widths, threshold, chunk, sta
         hi = min(b + wmax + m, nsamp)
         D = dedisperse(np.ascontiguousarray(x[:, lo:hi]), s, hi - lo, m)
         c, _ = single_pulse(D, lo, a, b, T, widths, threshold, stat_block, clip_sigma=clip_sigma,
-                            clip_iters=clip_iters)
+                            clip_iters=clip_iters, boxcar_full_width=boxcar_full_width)
         out.extend(c)
     out.sort(key=lambda c: (c[0], c[1]))
     return out

@@ -25,6 +25,13 @@ these readings:
 * S/N(d, t, w) = (float(sum_w) - wmu_w) * r_w. This is (sum - w mu) / (sigma sqrt w)
   with the rounding points fixed.
 * best(d, t) = max over w of S/N. wbest is the smallest width that attains it.
+* Optional decimated boxcar hierarchy (boxcar_full_width w0 > 0; the single-pulse search
+  the paper cites reaches wide boxcars on decimated data, where a width-w' boxcar over
+  sums of 2^l adjacent samples is the width-2^l w' boxcar of the plane at a start that is a
+  multiple of 2^l): width w is evaluated at the starts t that are multiples of its stride
+  s(w), the smallest power of two with w0 * s(w) >= w (s = 1 for w <= w0). The window
+  sums are unchanged, only the starts at which wide widths are tried are thinned. best and
+  wbest are over the widths evaluated at t; the first width must be <= w0.
 * Peak: (d, t) is a candidate iff best >= threshold and best is a 3x3 local maximum
   in (DM index, start). It must be strictly greater than the neighbours that come
   earlier in row-major (d, t) order, and >= the later ones. Neighbours outside
@@ -87,18 +94,34 @@ def block_norms(n, s1: list, s2: list, widths):
     return wmu, r
 
 
-def best_plane(prefix: np.ndarray, col0: int, lo: int, hi: int, widths, wmu, r):
+def boxcar_strides(widths, full_width: int):
+    """Stride of each width under the decimated boxcar hierarchy (all 1 if full_width is 0)."""
+    out = []
+    for w in widths:
+        s = 1
+        if full_width > 0:
+            while full_width * s < w:
+                s *= 2
+        out.append(s)
+    return out
+
+
+def best_plane(prefix: np.ndarray, col0: int, lo: int, hi: int, widths, wmu, r, strides=None):
     """best and wbest index for the starts [lo, hi). Row i uses wmu[i] and r[i].
 
     `prefix[:, k]` = sum of the first k plane columns, and plane column 0 is absolute
-    start `col0`.
+    start `col0`. strides: width k is tried only at starts that are multiples of
+    strides[k] (none: every start).
     """
     a = lo - col0
     best = None
     widx = None
+    starts = np.arange(lo, hi)
     for k, w in enumerate(widths):
         ssum = prefix[:, a + w:hi - col0 + w] - prefix[:, a:hi - col0]
         snr = (ssum.astype(np.float64) - wmu[:, k:k + 1]) * r[:, k:k + 1]
+        if strides is not None and strides[k] > 1:
+            snr = np.where((starts % strides[k] == 0)[None, :], snr, -np.inf)
         if best is None:
             best = snr
             widx = np.zeros(snr.shape, dtype=np.int64)
@@ -130,7 +153,8 @@ def candidates(center, v_prev, v_same, v_next, threshold):
 
 def single_pulse(D: np.ndarray, dd_t0: int, t_begin: int, t_end: int, t_total: int, widths,
                  threshold: float, stat_block: int, row0: int = 0, ndm: int | None = None,
-                 report_rows=None, want_best: bool = False, clip_sigma: float = 0.0, clip_iters: int = 0):
+                 report_rows=None, want_best: bool = False, clip_sigma: float = 0.0, clip_iters: int = 0,
+                 boxcar_full_width: int = 0):
     """Candidates for the starts [t_begin, t_end) of a dedispersed plane.
 
     D: int64 [nrows, ncols]. Row i is DM trial row0 + i, and column j is absolute
@@ -142,6 +166,9 @@ def single_pulse(D: np.ndarray, dd_t0: int, t_begin: int, t_end: int, t_total: i
     Returns (list of (d, t, width, snr_f32) sorted by (d, t), best plane or None).
     """
     widths = [int(w) for w in widths]
+    strides = boxcar_strides(widths, boxcar_full_width)
+    if strides[0] != 1:
+        raise ValueError("the first width must not exceed boxcar_full_width")
     nrows = D.shape[0]
     ndm = row0 + nrows if ndm is None else ndm
     wmax = max(widths)
@@ -173,7 +200,7 @@ def single_pulse(D: np.ndarray, dd_t0: int, t_begin: int, t_end: int, t_total: i
         wmu, r = block_norms(n, s1, s2, widths)
         lo = max(b0 - 1, 0)
         hi = b1 + 1 if (t_total < 0 or b1 + 1 <= t_total) else t_total
-        v, widx = best_plane(prefix, dd_t0, lo, hi, widths, wmu, r)
+        v, widx = best_plane(prefix, dd_t0, lo, hi, widths, wmu, r, strides)
         # pad to starts [b0 - 1, b1 + 1) with -inf outside the range of starts
         pad = np.full((nrows, (b1 + 1) - (b0 - 1)), neg)
         pad[:, lo - (b0 - 1):hi - (b0 - 1)] = v
