@@ -61,7 +61,8 @@ const char* aa_version(void);
  * not ascending, unique and >= 1, wmax > AA_MAX_WIDTH, nchan*255*wmax >= 2^32
  * (boxcar sums are exact 32-bit integers), a stat block that is not a positive
  * multiple of 256 or that could overflow int64 moments, or a threshold that is not
- * finite, a clip_sigma that is negative or not finite, or clip_iters outside 0..16.
+ * finite, a clip_sigma that is negative or not finite, clip_iters outside 0..16, or a
+ * boxcar_full_width that is negative or below the first width.
  * AA_ESHORT if T < 1. AA_EHIP or AA_ENOMEM if the upload fails.
  */
 #define AA_PLAN_HOST_ONLY 1u
@@ -86,6 +87,9 @@ typedef struct {
     float         clip_sigma;     /* outlier clipping of the block statistics, in sigma;
                                      0 = off (see aa_single_pulse)                   */
     int32_t       clip_iters;     /* clipping rounds, 0..16; 0 = off                 */
+    int32_t       boxcar_full_width; /* decimated boxcar hierarchy: widths above this are
+                                     tried on a coarser start grid (see aa_single_pulse);
+                                     0 = off, else >= widths[0]                        */
 } aa_plan_desc_t;
 
 typedef struct {
@@ -174,6 +178,11 @@ int aa_autotune(aa_plan_t plan, const uint8_t* d_in, int64_t in_pitch, int64_t n
  *     wmu_w = w*mu. r_w = 1/(sigma*sqrt(w)), or 0 if sigma == 0.
  *   - S/N(d,t,w) = (double(sum_{i<w} D[d][t+i]) - wmu_w) * r_w. best = max over w,
  *     and wbest is the smallest width that attains it.
+ *     With the plan's boxcar_full_width w0 > 0 (the decimated boxcar hierarchy of the
+ *     single-pulse work the paper cites: a boxcar over data decimated by 2^l is a wide
+ *     boxcar at a start that is a multiple of 2^l), width w is tried only at starts t
+ *     that are multiples of its stride, the smallest power of two s with w0 * s >= w;
+ *     best and wbest are over the widths tried at t.
  *   - (d,t) is a candidate iff best >= threshold and best is a 3x3 maximum in
  *     (d, t): strictly greater than the neighbours earlier in row-major order, and
  *     >= the later ones. Neighbours outside [0,ndm) x [0,t_total) are ignored. The

@@ -27,7 +27,7 @@ class PlanDesc(C.Structure):
                 ("foff_mhz", C.c_double), ("tsamp_s", C.c_double), ("dm", C.POINTER(C.c_double)),
                 ("ndm", C.c_int32), ("widths", C.POINTER(C.c_int32)), ("nwidths", C.c_int32),
                 ("snr_threshold", C.c_float), ("stat_block", C.c_int32), ("flags", C.c_uint32),
-                ("clip_sigma", C.c_float), ("clip_iters", C.c_int32)]
+                ("clip_sigma", C.c_float), ("clip_iters", C.c_int32), ("boxcar_full_width", C.c_int32)]
 
 
 class PlanInfo(C.Structure):

@@ -28,7 +28,7 @@ class Plan:
     """aa_plan: float64 shift table, sizes and the one-time device upload."""
 
     def __init__(self, nchan, nsamp, f_top, foff, tsamp, dms, widths, threshold, stat_block=0, host_only=False,
-                 clip_sigma=0.0, clip_iters=0):
+                 clip_sigma=0.0, clip_iters=0, boxcar_full_width=0):
         L = N.lib()
         self._dm = np.ascontiguousarray(np.asarray(dms, dtype=np.float64))
         self._w = np.ascontiguousarray(np.asarray(widths, dtype=np.int32))
@@ -47,6 +47,7 @@ class Plan:
         d.flags = N.AA_PLAN_HOST_ONLY if host_only else 0
         d.clip_sigma = float(clip_sigma)
         d.clip_iters = int(clip_iters)
+        d.boxcar_full_width = int(boxcar_full_width)
         h = C.c_void_p()
         N.check(L.aa_plan(C.byref(d), C.byref(h)))
         self._h = h
@@ -218,7 +219,7 @@ class RangePlan:
     """aa_range_plan: per-range time decimation over one plan description."""
 
     def __init__(self, nchan, nsamp, f_top, foff, tsamp, dms, widths, threshold, first, factor, stat_block=0,
-                 clip_sigma=0.0, clip_iters=0):
+                 clip_sigma=0.0, clip_iters=0, boxcar_full_width=0):
         self._dm = np.ascontiguousarray(np.asarray(dms, dtype=np.float64))
         self._w = np.ascontiguousarray(np.asarray(widths, dtype=np.int32))
         d = N.PlanDesc()
@@ -233,6 +234,7 @@ class RangePlan:
         d.flags = 0
         d.clip_sigma = float(clip_sigma)
         d.clip_iters = int(clip_iters)
+        d.boxcar_full_width = int(boxcar_full_width)
         fa = (C.c_int32 * len(first))(*[int(v) for v in first])
         fb = (C.c_int32 * len(factor))(*[int(v) for v in factor])
         h = C.c_void_p()

@@ -140,6 +140,7 @@ struct aa_plan_s {
     float threshold = 0;
     float clip_sigma = 0;                 // outlier clipping of the block statistics (0: off)
     int32_t clip_iters = 0;
+    int32_t boxcar_full_width = 0;        // decimated boxcar hierarchy (0: every width at every start)
     uint32_t flags = 0;
     std::vector<double> dm;
     std::vector<int32_t> widths;

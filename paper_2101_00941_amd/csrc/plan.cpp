@@ -100,6 +100,8 @@ extern "C" int aa_plan(const aa_plan_desc_t* desc, aa_plan_t* out) {
     if (!std::isfinite(q.snr_threshold)) return fail(AA_EINVAL, "aa_plan: threshold must be finite");
     if (!std::isfinite(q.clip_sigma) || q.clip_sigma < 0 || q.clip_iters < 0 || q.clip_iters > 16)
         return fail(AA_EINVAL, "aa_plan: clip_sigma must be finite and >= 0, clip_iters 0..16");
+    if (q.boxcar_full_width < 0 || (q.boxcar_full_width > 0 && q.boxcar_full_width < q.widths[0]))
+        return fail(AA_EINVAL, "aa_plan: boxcar_full_width must be 0 or at least the first width");
     const int32_t B = q.stat_block == 0 ? 32768 : q.stat_block;
     if (B < kSpsTile || B % kSpsTile) return fail(AA_EINVAL, "aa_plan: stat_block must be a positive multiple of 256");
     {
@@ -122,6 +124,7 @@ extern "C" int aa_plan(const aa_plan_desc_t* desc, aa_plan_t* out) {
     p->threshold = q.snr_threshold;
     p->clip_sigma = q.clip_sigma;
     p->clip_iters = q.clip_sigma > 0 ? q.clip_iters : 0;
+    p->boxcar_full_width = q.boxcar_full_width;
     p->flags = q.flags;
     p->dm.assign(q.dm, q.dm + q.ndm);
     p->widths.assign(q.widths, q.widths + q.nwidths);

@@ -37,6 +37,10 @@ struct SpsConst {
     int32_t wmax;
     int32_t widths[kMaxWidths];
     double sqrtw[kMaxWidths];
+    // decimated boxcar hierarchy: widths kfull .. nw-1 are tried only at starts t with
+    // (t & smask[k]) == 0 (stride - 1); kfull = nw when the hierarchy is off
+    int32_t kfull;
+    int32_t smask[kMaxWidths];
 };
 
 typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
@@ -180,12 +184,13 @@ __host__ __device__ inline DetectLds detect_lds(int wmax, int nw, bool exact) {
 // Exact value of one halo cell: best S/N over the widths, float64, same operation order
 // as the oracle. -inf outside the range of rows and starts.
 __device__ __forceinline__ double exact_best(const uint32_t* pre, int stride, const double* nj, int d0,
-                                             const SpsConst& sc, int r, int c, bool valid) {
+                                             const SpsConst& sc, int r, int c, bool valid, uint32_t t) {
     if (!valid) return -__builtin_huge_val();
     const uint32_t* pr = pre + r * stride + c;
     const double* nr = nj + static_cast<int64_t>(d0 - 1 + r) * (2 * sc.nw);   // halo row r is trial d0 - 1 + r
     double v = 0.0;
     for (int k = 0; k < sc.nw; ++k) {
+        if (k >= sc.kfull && (t & static_cast<uint32_t>(sc.smask[k]))) continue;   // not on this width's grid
         const uint32_t s = pr[sc.widths[k]] - pr[0];
         const double snr = (static_cast<double>(s) - nr[k]) * nr[sc.nw + k];
         if (k == 0 || snr > v) v = snr;
@@ -339,7 +344,8 @@ __global__ __launch_bounds__(256) void sps_detect_kernel(
             const int r = i / kHaloCols, c = i - r * kHaloCols;
             const int d = d0 - 1 + r;
             const int64_t t = tt0 - 1 + c;
-            best[i] = exact_best(pre, ps, nj, d0, sc, r, c, d >= 0 && d < ndm && t >= lo && t < hi);
+            best[i] = exact_best(pre, ps, nj, d0, sc, r, c, d >= 0 && d < ndm && t >= lo && t < hi,
+                                 static_cast<uint32_t>(t));
         }
         __syncthreads();
         // 3x3 peak test for the inner rows, 64 consecutive starts per wave step
@@ -387,7 +393,7 @@ __global__ __launch_bounds__(256) void sps_detect_kernel(
             const int nsm0 = static_cast<int>(0u - smin[0]);   // lane k: minus width k's threshold
             const int nsm1 = static_cast<int>(0u - smin[1]);
 #pragma unroll 3
-            for (int k = 0; k < nw; ++k) {
+            for (int k = 0; k < sc.kfull; ++k) {
                 const int w = __builtin_amdgcn_readlane(wlane, k);
                 const uint32_t nsk0 = static_cast<uint32_t>(__builtin_amdgcn_readlane(nsm0, k));
                 const uint32_t nsk1 = static_cast<uint32_t>(__builtin_amdgcn_readlane(nsm1, k));
@@ -396,6 +402,21 @@ __global__ __launch_bounds__(256) void sps_detect_kernel(
                 for (int q = 0; q < 4; ++q) {
                     margin[0][q] = max(margin[0][q], static_cast<int32_t>(pr0[64 * q + w] + neg0[0][q] + nsk0));
                     margin[1][q] = max(margin[1][q], static_cast<int32_t>(pr1[64 * q + w] + neg0[1][q] + nsk1));
+                }
+            }
+            // widths of the decimated hierarchy: only starts on the width's grid count
+#pragma unroll 1
+            for (int k = sc.kfull; k < nw; ++k) {
+                const int w = __builtin_amdgcn_readlane(wlane, k);
+                const uint32_t nsk0 = static_cast<uint32_t>(__builtin_amdgcn_readlane(nsm0, k));
+                const uint32_t nsk1 = static_cast<uint32_t>(__builtin_amdgcn_readlane(nsm1, k));
+                const uint32_t sm = static_cast<uint32_t>(sc.smask[k]);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if ((static_cast<uint32_t>(tt0 + 64 * q + lane) & sm) == 0) {
+                        margin[0][q] = max(margin[0][q], static_cast<int32_t>(pr0[64 * q + w] + neg0[0][q] + nsk0));
+                        margin[1][q] = max(margin[1][q], static_cast<int32_t>(pr1[64 * q + w] + neg0[1][q] + nsk1));
+                    }
                 }
             }
         }
@@ -416,7 +437,8 @@ __global__ __launch_bounds__(256) void sps_detect_kernel(
                     auto val = [&](int rr_, int cc) {
                         const int dr = d0 - 1 + rr_;
                         const int64_t tr = tt0 - 1 + cc;
-                        return exact_best(pre, ps, nj, d0, sc, rr_, cc, dr >= 0 && dr < ndm && tr >= lo && tr < hi);
+                        return exact_best(pre, ps, nj, d0, sc, rr_, cc, dr >= 0 && dr < ndm && tr >= lo && tr < hi,
+                                          static_cast<uint32_t>(tr));
                     };
                     const int c0 = 64 * q + lane + 1;
                     const double x = val(r, c0);
@@ -517,6 +539,7 @@ __global__ __launch_bounds__(256) void sps_emit_kernel(
                     const uint32_t base = carry + (incl - p3);
                     const uint32_t pre4[4] = {base + x[0], base + p1, base + p2, base + p3};
                     for (; q < sc.nw && sc.widths[q] <= c0 + 256; ++q) {
+                        if (q >= sc.kfull && (static_cast<uint32_t>(t) & static_cast<uint32_t>(sc.smask[q]))) continue;
                         const int ix = sc.widths[q] - 1 - c0;    // sum of the first widths[q] samples
                         const uint32_t sel = pre4[ix & 3];
                         const uint32_t S = static_cast<uint32_t>(__shfl(static_cast<int>(sel), ix >> 2, 64));
@@ -583,9 +606,15 @@ int launch_single_pulse(const aa_plan_s* p, const int32_t* d_dd, int64_t dd_pitc
     SpsConst sc{};
     sc.nw = p->nwidths;
     sc.wmax = p->wmax;
+    sc.kfull = p->nwidths;
     for (int k = 0; k < p->nwidths; ++k) {
         sc.widths[k] = p->widths[k];
         sc.sqrtw[k] = p->sqrtw[k];
+        int64_t stride = 1;   // smallest power of two with full_width * stride >= width
+        if (p->boxcar_full_width > 0)
+            while (static_cast<int64_t>(p->boxcar_full_width) * stride < p->widths[k]) stride *= 2;
+        sc.smask[k] = static_cast<int32_t>(stride - 1);
+        if (stride > 1 && sc.kfull == p->nwidths) sc.kfull = k;   // widths ascend: the rest are strided too
     }
     hipLaunchKernelGGL(sps_stats_kernel, dim3(static_cast<unsigned>(L.nblk), static_cast<unsigned>(p->ndm)), dim3(256),
                        0, stream, d_dd, dd_pitch, dd_t0, t_begin, t_end, p->stat_block, p->ndm, sc,

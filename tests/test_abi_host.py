@@ -147,3 +147,11 @@ def test_plan_rejects_bad_clipping():
             Plan(64, 20000, 1500.0, 1.5, 64e-6, np.arange(10.0), [1, 2], 6.0, clip_sigma=c, clip_iters=it,
                  host_only=True)
     Plan(64, 20000, 1500.0, 1.5, 64e-6, np.arange(10.0), [1, 2], 6.0, clip_sigma=3.0, clip_iters=16, host_only=True)
+
+
+def test_plan_rejects_bad_boxcar_hierarchy():
+    from paper_2101_00941_amd import AAError, Plan
+    for w0 in (-1, 1):
+        with pytest.raises(AAError):
+            Plan(64, 20000, 1500.0, 1.5, 64e-6, np.arange(10.0), [2, 4], 6.0, boxcar_full_width=w0, host_only=True)
+    Plan(64, 20000, 1500.0, 1.5, 64e-6, np.arange(10.0), [2, 4], 6.0, boxcar_full_width=2, host_only=True)
