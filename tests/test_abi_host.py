@@ -155,3 +155,16 @@ def test_plan_rejects_bad_boxcar_hierarchy():
         with pytest.raises(AAError):
             Plan(64, 20000, 1500.0, 1.5, 64e-6, np.arange(10.0), [2, 4], 6.0, boxcar_full_width=w0, host_only=True)
     Plan(64, 20000, 1500.0, 1.5, 64e-6, np.arange(10.0), [2, 4], 6.0, boxcar_full_width=2, host_only=True)
+
+
+def test_plain_c_caller(tmp_path):
+    """A C program (no Python) links the library and calls host-side entry points."""
+    from paper_2101_00941_amd import _native
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    exe = tmp_path / "abi_c"
+    libdir = os.path.dirname(_native.LIB_PATH)
+    subprocess.run(["gcc", "-std=c99", "-O1", "-Wall", "-I", os.path.join(root, "include"),
+                    os.path.join(root, "tests", "host", "abi_c_check.c"), "-L", libdir, "-l:libaa_mi355x.so",
+                    f"-Wl,-rpath,{libdir}", "-o", str(exe), "-lm"], check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stdout + r.stderr
