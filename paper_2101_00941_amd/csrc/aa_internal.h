@@ -41,11 +41,13 @@ struct DedispVariant {
                      //    residuals per step, see below
                      // 5: the same contraction with 8 channels x 4 residuals per step
                      // 6: layouts 5 and 4 mixed by trial range (per DM block)
+                     // 7: quads of channels staged per residual pattern, v_sad_u8 sums
     int tile;        // output samples per work-group (time tile)
-    int depth;       // staging buffers in the LDS ring (loads run depth - 1 steps ahead)
+    int depth;       // staging buffers in the LDS ring (loads run depth - 1 steps ahead);
+                     // layout 7: staging chunks per step (64 units of 16 bytes each)
     int max_tiles;   // layouts 4-6: a channel block spans at most 32 * max_tiles rows of t' (31 or 63)
 };
-constexpr int kNumDedispVariants = 21;
+constexpr int kNumDedispVariants = 25;
 static_assert(kNumDedispVariants <= AA_MAX_VARIANTS, "aa_batch_info_t::tune_ms holds every variant");
 
 // Matrix-core variants (layouts 4-6). Within a block of up to 32 trials (first trial d0)
@@ -84,6 +86,35 @@ constexpr MfmaRec mfma_rec(int cps) {
 constexpr int mfma_lds_bytes(int tile, int depth, int max_tiles, int cps = 4) {
     return (tile + 2) * 32 * 4 + depth * (cps * mfma_row_bytes(max_tiles) + mfma_rec(cps).size);
 }
+// Quad variants (layout 7): shift-and-add on the vector ALUs, no matrix cores. A step
+// is one quad of channels c_i = 4q + i. Within a DM block, trials whose residuals
+// r_i = s[d][c_i] - s[d][c_0] (i = 1..3) agree share a pattern. Per step, each pattern
+// is staged once as dwords holding one sample of the four channels,
+//   Y[k] = (X[c0][t0 + lo + k], X[c1][t0 + lo + r1 + k], X[c2][.. + r2 ..], X[c3][.. + r3 ..]),
+// with lo the smallest s[d][c0] over the pattern's trials, and trial d adds the dword
+// Y[s[d][c0] - lo + t] into output sample t with one v_sad_u8 (four byte-adds).
+// A work-group stages a step in 64-unit chunks (a unit is 4 dwords); chunk j belongs
+// to wave j % waves and fills dwords [256 j, 256 j + 256) of the step buffer. Pattern p
+// takes ceil(units_p / 64) consecutive chunks from chunk cb_p (the earlier patterns'
+// chunks), units_p = ceil((tile + hi - lo) / 4).
+// Records, nq + 1 per DM block, quad_rec_dwords(chunks) int32 each (a multiple of 64):
+// record e holds
+//   [0, 16)           byte offsets in the step buffer of the trials' windows at step e - 1,
+//                     4 (256 cb_p + s[d][c0] - lo_p), two u16 per dword (trial 2i in the
+//                     low half of dword i; 0 for absent trials and for e = 0)
+//   32                chunks of step e (0 for e = nq)
+//   64 + 4 j + i      row offset of channel i for chunk j of step e: lo_p + r_i + 256 c,
+//                     c = j - cb_p (relative to the time tile; its low 2 bits are the
+//                     byte phase of the row within a dword)
+// so that one record serves the sums of step e - 1 and the staging of step e.
+// Channels past nchan stage zero bytes and have r = 0.
+constexpr int kQuadTrials = 32;
+constexpr int kQuadMaxPat = 8;
+constexpr int quad_rec_dwords(int chunks) { return (64 + 4 * chunks + 63) / 64 * 64; }
+constexpr int kQuadMaxResidual = 1023;
+constexpr int kQuadMaxChunks = 64;   // trial offsets stay below 64 KB
+constexpr int quad_lds_bytes(int chunks) { return 2 * chunks * 1024; }
+
 extern const DedispVariant kDedispVariants[kNumDedispVariants];
 constexpr int kDefaultDedispVariant = 12;   // i8 matrix cores, 16 waves
 
@@ -98,7 +129,7 @@ struct DmBlock {
     int32_t rs_lo;   // layouts 4-6: smallest and largest staged-row start over the block's
     int32_t rs_hi;   // channels, relative to the time tile (0 for the other layouts)
     int32_t cps;     // layouts 4-6: channels per matrix step of this block (4 or 8)
-    int32_t rec256;  // layouts 4-6: offset of the block's records in 256-byte units
+    int32_t rec256;  // layouts 4-7: offset of the block's records in 256-byte units
 };
 
 // Per-variant tables. For block b and channel c:
@@ -165,6 +196,10 @@ int prepare_variant(aa_plan_s* p, int variant);
 // it on, the split taken from a cost estimate, or split_at when that is >= 0.
 int build_mfma_tables(const aa_plan_s* p, int tile, int depth, int max_tiles, int cps, std::vector<DmBlock>& blocks,
                       std::vector<int32_t>& rsv, std::vector<uint8_t>& rec, int split_at = -1);
+// Host tables of the quad variants: DM blocks (rec256 = first record, in 256-byte
+// units) and the records [block][nq + 1][quad_rec_dwords(chunks)].
+int build_quad_tables(const aa_plan_s* p, int tile, int chunks, std::vector<DmBlock>& blocks,
+                      std::vector<int32_t>& rec);
 void free_tables(DedispTables& t);
 // Launchers (dedisp.hip, sps.hip). Arguments are validated by the callers.
 int launch_dedisperse(const aa_plan_s* p, int variant, const uint8_t* d_in, int64_t in_pitch, int64_t n_in,

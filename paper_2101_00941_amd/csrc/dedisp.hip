@@ -698,6 +698,153 @@ __device__ __forceinline__ void dedisp_mfma_tile(const DedispArgs& A, int blk, i
     }
 }
 
+// Layout 7: shift-and-add on the vector ALUs with one v_sad_u8 per 4 byte-adds (step
+// records in aa_internal.h). Thread i owns output samples t0 + i + 64 W j, j < J, of
+// all 32 trials of the block. Per step (a quad of channels):
+//  * the chunks of the next step are loaded from the input rows into registers (two
+//    aligned dwords per channel and unit, raw buffer loads), then the current step is
+//    summed, then the loaded rows are aligned (v_alignbyte_b32), transposed 4x4 bytes
+//    (8 v_perm_b32) into four sample dwords and written to the other LDS buffer;
+//  * summing one trial: J dwords one 64 W stride apart (ds_read2st64_b32) at the
+//    trial's recorded offset go through v_sad_u8 into 32-bit accumulators. Consecutive
+//    lanes read consecutive dwords: no bank conflicts.
+// Records are read with scalar loads; each chunk's four row offsets come precomputed,
+// so staging a chunk costs four scalar ops. Each channel row has its own buffer
+// resource spanning [0, n_in16) (empty for channels past nchan): the range check of raw
+// buffer loads returns zero for the dwords outside it.
+__device__ __forceinline__ void lds_step_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+constexpr int kRawBufferFlags = 0x00020000;   // word 3 of a gfx9 buffer resource: raw 32-bit data
+
+template <int W, int J, int CPW>
+__device__ __forceinline__ void dedisp_quad_tile(const DedispArgs& A, int blk, int64_t t0) {
+    constexpr int NT = 64 * W, CH = W * CPW, BUFB = CH * 1024, RD = quad_rec_dwords(CH);
+    constexpr int NTR = kQuadTrials;
+    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const DmBlock b = A.blocks[blk];
+    const int nq = A.nchan_pad >> 2, nchan = A.nchan, count = b.count;
+    const int64_t pitch = A.in_pitch;
+    const int32_t n_in16 = static_cast<int32_t>(A.n_in16);
+    // records are read-only for the launch: the constant address space makes their
+    // (uniform) reads scalar loads
+    typedef const __attribute__((address_space(4))) int32_t* rec_ptr;
+    const rec_ptr R = (rec_ptr)(A.offs) + static_cast<int64_t>(b.rec256) * 64;
+    const uint32_t lane_t0 = 4u * static_cast<uint32_t>(lane) + static_cast<uint32_t>(t0);
+    uint8_t* const wdst = lds + 16 * lane + 1024 * wave;   // this lane's unit in chunk `wave`
+
+    uint32_t acc[NTR][J];
+#pragma unroll
+    for (int d = 0; d < NTR; ++d)
+#pragma unroll
+        for (int j = 0; j < J; ++j) acc[d][j] = 0;
+
+    // staging registers of one step: per chunk slot, two aligned dwords per channel
+    uint32_t sw[CPW][4][2];
+    // the current record, in scalar registers: trial offsets of the step being summed,
+    // and the chunk count and this wave's chunk row offsets of the step being staged.
+    // The next record is read at the end of each step, so that the barrier's wait covers
+    // its latency and no scalar load is in flight while the sums wait for LDS reads.
+    uint32_t toff[NTR / 2];   // two u16 trial offsets per dword
+    int32_t co[CPW][4];
+    int nch = 0;
+    auto load_rec = [&](rec_ptr E) {
+#pragma unroll
+        for (int d = 0; d < NTR / 2; ++d) toff[d] = static_cast<uint32_t>(E[d]);
+        nch = E[32];
+#pragma unroll
+        for (int m = 0; m < CPW; ++m)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) co[m][i] = E[64 + 4 * (wave + W * m) + i];
+    };
+
+    auto issue = [&](int q) {
+        __amdgpu_buffer_rsrc_t rs[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            rs[i] = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(A.in + static_cast<int64_t>(4 * q + i) * pitch),
+                                                      0, 4 * q + i < nchan ? n_in16 : 0, kRawBufferFlags);
+#pragma unroll
+        for (int m = 0; m < CPW; ++m) {
+            if (wave + W * m < nch) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const uint32_t voff = lane_t0 + static_cast<uint32_t>(co[m][i] & ~3);
+                    sw[m][i][0] = static_cast<uint32_t>(__builtin_amdgcn_raw_buffer_load_b32(rs[i], voff, 0, 0));
+                    sw[m][i][1] = static_cast<uint32_t>(__builtin_amdgcn_raw_buffer_load_b32(rs[i], voff + 4u, 0, 0));
+                }
+            }
+        }
+    };
+
+    auto write = [&](int buf) {
+#pragma unroll
+        for (int m = 0; m < CPW; ++m) {
+            if (wave + W * m < nch) {
+                uint32_t v[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    v[i] = __builtin_amdgcn_alignbyte(sw[m][i][1], sw[m][i][0], static_cast<uint32_t>(co[m][i]));
+                // 4x4 byte transpose: o[k] = (v0.byte k, v1.byte k, v2.byte k, v3.byte k)
+                const uint32_t t0l = __builtin_amdgcn_perm(v[1], v[0], 0x05010400u);
+                const uint32_t t0h = __builtin_amdgcn_perm(v[1], v[0], 0x07030602u);
+                const uint32_t t1l = __builtin_amdgcn_perm(v[3], v[2], 0x05010400u);
+                const uint32_t t1h = __builtin_amdgcn_perm(v[3], v[2], 0x07030602u);
+                const u32x4 o = {__builtin_amdgcn_perm(t1l, t0l, 0x05040100u), __builtin_amdgcn_perm(t1l, t0l, 0x07060302u),
+                                 __builtin_amdgcn_perm(t1h, t0h, 0x05040100u), __builtin_amdgcn_perm(t1h, t0h, 0x07060302u)};
+                *reinterpret_cast<u32x4*>(wdst + buf * BUFB + 1024 * W * m) = o;
+            }
+        }
+    };
+
+    load_rec(R);
+    issue(0);
+    write(0);
+    load_rec(R + RD);
+    lds_step_barrier();
+    for (int k = 0; k < nq; ++k) {
+        const bool more = k + 1 < nq;
+        if (more) issue(k + 1);
+        const uint8_t* y = lds + (k & 1) * BUFB + 4 * tid;
+        // trials in groups of 8; a block's absent trials (short blocks) are skipped per group
+#pragma unroll
+        for (int g = 0; g < NTR / 8; ++g) {
+            if (8 * g < count) {
+#pragma unroll
+                for (int d = 8 * g; d < 8 * g + 8; ++d) {
+                    const uint32_t off = (d & 1) ? toff[d >> 1] >> 16 : toff[d >> 1] & 0xFFFFu;
+                    const uint32_t* yd = reinterpret_cast<const uint32_t*>(y + off);
+#pragma unroll
+                    for (int j = 0; j < J; ++j) acc[d][j] = __builtin_amdgcn_sad_u8(yd[NT * j], 0u, acc[d][j]);
+                }
+            }
+        }
+        if (more) {
+            write((k + 1) & 1);
+            asm volatile("" ::: "memory");
+            load_rec(R + static_cast<int64_t>(k + 2) * RD);   // offsets of step k + 1, chunks of step k + 2
+        }
+        lds_step_barrier();
+    }
+
+#pragma unroll
+    for (int d = 0; d < NTR; ++d) {
+        if (d < count) {
+            int32_t* orow = A.out + static_cast<int64_t>(b.first + d) * A.out_pitch;
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                const int64_t t = t0 + tid + NT * j;
+                if (t < A.n_out) orow[t] = static_cast<int32_t>(acc[d][j]);
+            }
+        }
+    }
+}
+
 // Layout 6: the DM block's own step shape (the whole work-group takes one branch).
 template <int W, int TILE, int DEPTH, int MAXT>
 __device__ __forceinline__ void dedisp_mfma_mixed(const DedispArgs& A, int blk, int64_t t0) {
@@ -712,7 +859,9 @@ __device__ __forceinline__ void dedisp_mfma_mixed(const DedispArgs& A, int blk, 
 template <int DPW, int W, int LAYOUT, int TILE = kTimeTile, int DEPTH = 2, int MAXT = 63, int WPE = 1>
 __global__ __launch_bounds__(64 * W, WPE) void dedisp_kernel(DedispArgs a) {
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
-    if constexpr (LAYOUT == 6)
+    if constexpr (LAYOUT == 7)
+        dedisp_quad_tile<W, DPW, DEPTH>(a, bid % a.nblk, static_cast<int64_t>(bid / a.nblk) * TILE);
+    else if constexpr (LAYOUT == 6)
         dedisp_mfma_mixed<W, TILE, DEPTH, MAXT>(a, bid % a.nblk, static_cast<int64_t>(bid / a.nblk) * TILE);
     else if constexpr (LAYOUT == 4 || LAYOUT == 5)
         dedisp_mfma_tile<W, TILE, DEPTH, MAXT, mfma_cps(LAYOUT)>(a, bid % a.nblk, static_cast<int64_t>(bid / a.nblk) * TILE);
@@ -748,7 +897,9 @@ __global__ __launch_bounds__(64 * W, WPE) void dedisp_batch_kernel(const DedispA
         }
         const DedispArgs a = args[lo];
         const int64_t local = it - item_begin[lo];
-        if constexpr (LAYOUT == 6)
+        if constexpr (LAYOUT == 7)
+            dedisp_quad_tile<W, DPW, DEPTH>(a, static_cast<int>(local % a.nblk), (local / a.nblk) * TILE);
+        else if constexpr (LAYOUT == 6)
             dedisp_mfma_mixed<W, TILE, DEPTH, MAXT>(a, static_cast<int>(local % a.nblk), (local / a.nblk) * TILE);
         else if constexpr (LAYOUT == 4 || LAYOUT == 5)
             dedisp_mfma_tile<W, TILE, DEPTH, MAXT, mfma_cps(LAYOUT)>(a, static_cast<int>(local % a.nblk),
@@ -764,13 +915,15 @@ __global__ void reset_counter_kernel(unsigned long long* c) { *c = 0ull; }
 typedef void (*DedispFn)(DedispArgs);
 typedef void (*DedispBatchFn)(const DedispArgs*, const int64_t*, int, int64_t, unsigned long long*);
 
-// Indexed by DedispVariant::id (tiling.cpp); layout-4 entries repeat the variant's
-// time tile, depth and channel-block span.
+// Indexed by DedispVariant::id (tiling.cpp); layout 4-6 entries repeat the variant's
+// time tile, depth and channel-block span; layout 7 entries are <samples per lane, waves,
+// 7, tile, chunks per wave, 0, waves per SIMD>.
 #define AA_VARIANTS(K)                                                                           \
     K<4, 4, 1>, K<2, 8, 1>, K<4, 8, 1>, K<2, 16, 1>, K<2, 8, 0>, K<4, 4, 0>, K<2, 8, 3>, K<4, 4, 3>, \
         K<2, 8, 2>, K<4, 8, 2>, K<4, 4, 2>, K<4, 8, 4, 1024, 3>, K<2, 16, 4, 1024, 3>, K<2, 16, 4, 768, 7>, \
         K<4, 8, 4, 512, 3, 31, 4>, K<2, 16, 4, 512, 3, 31, 8>, K<4, 8, 4, 480, 4, 31, 4>, K<2, 16, 5, 864, 3, 63>, \
-        K<2, 16, 4, 960, 4, 63>, K<2, 16, 4, 896, 5, 63>, K<2, 16, 6, 864, 3, 63>
+        K<2, 16, 4, 960, 4, 63>, K<2, 16, 4, 896, 5, 63>, K<2, 16, 6, 864, 3, 63>, K<4, 4, 7, 1024, 8, 0, 2>, \
+        K<2, 8, 7, 1024, 4, 0, 4>, K<4, 8, 7, 2048, 8, 0, 2>, K<2, 8, 7, 1024, 6, 0, 2>
 const DedispFn kKernels[kNumDedispVariants] = {AA_VARIANTS(dedisp_kernel)};
 const DedispBatchFn kBatchKernels[kNumDedispVariants] = {AA_VARIANTS(dedisp_batch_kernel)};
 #undef AA_VARIANTS
@@ -810,6 +963,8 @@ int launch_dedisperse(const aa_plan_s* p, int variant, const uint8_t* d_in, int6
     if (T.variant != variant || !T.d_offs) return fail(AA_EINVAL, "aa_dedisperse: variant tables not prepared");
     const DedispVariant& V = kDedispVariants[variant];
     const DedispArgs a = dedisp_args(p, variant, d_in, in_pitch, n_in, d_out, out_pitch);
+    if (V.layout == 7 && a.n_in16 > (int64_t{1} << 30))
+        return fail(AA_EINVAL, "aa_dedisperse: the quad variants take rows of at most 2^30 samples");
     const int64_t grid = a.ntile * a.nblk;
     if (grid > 0x7fffffff) return fail(AA_EINVAL, "aa_dedisperse: too many tiles for one launch");
     const size_t lds = V.layout >= 4 ? static_cast<size_t>(V.lds_bytes) : static_cast<size_t>(2 * kChanPerPass) * T.max_row;

@@ -38,6 +38,12 @@ const DedispVariant kDedispVariants[kNumDedispVariants] = {
     {19, 16, 2, mfma_lds_bytes(896, 5, 63), 4, 896, 5, 63},     // 1024 threads, 4 tiles per wave
     // step shape per DM block: 8 x 4 below a split trial, 4 x 8 above it
     {20, 16, 2, mfma_lds_bytes(864, 3, 63, 8), 6, 864, 3, 63},  // 1024 threads, 4 tiles per wave
+    // shift-and-add with v_sad_u8 on channel quads staged per residual pattern, 32 trials
+    // per block; tile = 64 * waves * samples per lane, depth = staging chunks per step
+    {21, 4, 8, quad_lds_bytes(32), 7, 1024, 32, 0},   // 256 threads, 4 samples per lane
+    {22, 8, 4, quad_lds_bytes(32), 7, 1024, 32, 0},   // 512 threads, 2 samples per lane
+    {23, 8, 4, quad_lds_bytes(64), 7, 2048, 64, 0},   // 512 threads, 4 samples per lane
+    {24, 8, 4, quad_lds_bytes(48), 7, 1024, 48, 0},   // 512 threads, 2 samples per lane
 };
 
 void free_tables(DedispTables& t) {
@@ -280,7 +286,157 @@ int build_mfma_tables(const aa_plan_s* p, int tile, int depth, int max_tiles, in
     return AA_OK;
 }
 
+// Tables of the quad variants (layout 7). A DM block grows trial by trial while, in
+// every step (quad of channels), the block's trials form at most kQuadMaxPat residual
+// patterns whose staged dwords fill at most `chunks` 64-unit chunks. One trial always
+// fits: its step has one pattern of tile / 4 units.
 namespace {
+
+struct QuadPat {
+    int32_t r1, r2, r3, lo, hi;
+};
+
+int64_t quad_units(int tile, int32_t lo, int32_t hi) { return (static_cast<int64_t>(tile) + hi - lo + 3) / 4; }
+
+}  // namespace
+
+int build_quad_tables(const aa_plan_s* p, int tile, int chunks, std::vector<DmBlock>& blocks,
+                      std::vector<int32_t>& rec) {
+    const int nchan = p->nchan, nq = (nchan + 3) / 4;
+    if (tile % 256 != 0 || static_cast<int64_t>(tile) / 256 > chunks || chunks > kQuadMaxChunks)
+        return fail(AA_EINVAL, "quad tiling: a one-trial step does not fit the chunks");
+    auto S = [&](int d, int c) { return p->shifts[static_cast<size_t>(d) * nchan + c]; };
+    auto key = [&](int d, int q, int32_t (&r)[3]) {
+        const int32_t s0 = S(d, 4 * q);
+        for (int i = 1; i < 4; ++i) r[i - 1] = 4 * q + i < nchan ? S(d, 4 * q + i) - s0 : 0;
+        return s0;
+    };
+    for (int d = 0; d < p->ndm; ++d)
+        for (int q = 0; q < nq; ++q) {
+            int32_t r[3];
+            key(d, q, r);
+            for (int32_t v : r)
+                if (v < 0 || v > kQuadMaxResidual)
+                    return fail(AA_EINVAL, "quad tiling: a residual within a channel quad exceeds 1023 samples");
+        }
+    blocks.clear();
+    std::vector<std::vector<QuadPat>> st(nq);
+    for (int d0 = 0; d0 < p->ndm;) {
+        for (auto& v : st) v.clear();
+        int count = 0;
+        while (count < kQuadTrials && d0 + count < p->ndm) {
+            const int d = d0 + count;
+            bool ok = true;
+            for (int q = 0; q < nq && ok; ++q) {
+                int32_t r[3];
+                const int32_t s0 = key(d, q, r);
+                int64_t used = 0;
+                bool found = false;
+                for (const QuadPat& P : st[q]) {
+                    int32_t lo = P.lo, hi = P.hi;
+                    if (P.r1 == r[0] && P.r2 == r[1] && P.r3 == r[2]) {
+                        lo = std::min(lo, s0);
+                        hi = std::max(hi, s0);
+                        found = true;
+                    }
+                    used += (quad_units(tile, lo, hi) + 63) / 64;
+                }
+                if (!found) {
+                    if (static_cast<int>(st[q].size()) >= kQuadMaxPat) ok = false;
+                    used += (quad_units(tile, s0, s0) + 63) / 64;
+                }
+                if (used > chunks) ok = false;
+            }
+            if (!ok) break;
+            for (int q = 0; q < nq; ++q) {
+                int32_t r[3];
+                const int32_t s0 = key(d, q, r);
+                bool found = false;
+                for (QuadPat& P : st[q])
+                    if (P.r1 == r[0] && P.r2 == r[1] && P.r3 == r[2]) {
+                        P.lo = std::min(P.lo, s0);
+                        P.hi = std::max(P.hi, s0);
+                        found = true;
+                    }
+                if (!found) st[q].push_back(QuadPat{r[0], r[1], r[2], s0, s0});
+            }
+            ++count;
+        }
+        if (count < 1) return fail(AA_EINVAL, "quad tiling: a single trial does not fit");
+        blocks.push_back(DmBlock{d0, count, 0, 0, 0, 4, 0});
+        d0 += count;
+    }
+    // records: entry e of a block holds the trial offsets of step e - 1 and the chunks
+    // of step e (entries 0 .. nq)
+    const size_t nblk = blocks.size(), nrec = static_cast<size_t>(nq) + 1;
+    const size_t rd = static_cast<size_t>(quad_rec_dwords(chunks));
+    rec.assign(nblk * nrec * rd, 0);
+    for (size_t bi = 0; bi < nblk; ++bi) {
+        DmBlock& b = blocks[bi];
+        b.rec256 = static_cast<int32_t>(bi * nrec * rd / 64);
+        for (int q = 0; q < nq; ++q) {
+            std::vector<QuadPat> pats;
+            std::vector<int> which(b.count);
+            for (int i = 0; i < b.count; ++i) {
+                int32_t r[3];
+                const int32_t s0 = key(b.first + i, q, r);
+                int k = 0;
+                while (k < static_cast<int>(pats.size()) &&
+                       !(pats[k].r1 == r[0] && pats[k].r2 == r[1] && pats[k].r3 == r[2]))
+                    ++k;
+                if (k == static_cast<int>(pats.size())) pats.push_back(QuadPat{r[0], r[1], r[2], s0, s0});
+                pats[k].lo = std::min(pats[k].lo, s0);
+                pats[k].hi = std::max(pats[k].hi, s0);
+                which[i] = k;
+            }
+            int32_t* P = &rec[(bi * nrec + q) * rd];        // chunks of step q
+            int32_t* O = &rec[(bi * nrec + q + 1) * rd];    // trial offsets of step q
+            int64_t nch = 0;
+            std::vector<int64_t> first_chunk(pats.size());
+            for (size_t k = 0; k < pats.size(); ++k) {
+                const QuadPat& Q = pats[k];
+                const int64_t units = quad_units(tile, Q.lo, Q.hi), n = (units + 63) / 64;
+                first_chunk[k] = nch;
+                if (pats.size() > static_cast<size_t>(kQuadMaxPat) || nch + n > chunks)
+                    return fail(AA_EINVAL, "quad tiling: step tables exceed the chunk budget");
+                for (int64_t c = 0; c < n; ++c) {
+                    int32_t* C = P + 64 + 4 * (nch + c);
+                    C[0] = static_cast<int32_t>(Q.lo + 256 * c);
+                    C[1] = static_cast<int32_t>(Q.lo + Q.r1 + 256 * c);
+                    C[2] = static_cast<int32_t>(Q.lo + Q.r2 + 256 * c);
+                    C[3] = static_cast<int32_t>(Q.lo + Q.r3 + 256 * c);
+                }
+                nch += n;
+            }
+            P[32] = static_cast<int32_t>(nch);
+            for (int i = 0; i < b.count; ++i) {
+                const QuadPat& Q = pats[which[i]];
+                const uint32_t off = static_cast<uint32_t>(4 * (256 * first_chunk[which[i]] + S(b.first + i, 4 * q) - Q.lo));
+                O[i / 2] = static_cast<int32_t>(static_cast<uint32_t>(O[i / 2]) | (off << (16 * (i & 1))));
+            }
+        }
+    }
+    return AA_OK;
+}
+
+namespace {
+int prepare_quad(const aa_plan_s* p, const DedispVariant& V, DedispTables& t) {
+    std::vector<DmBlock> blocks;
+    std::vector<int32_t> rec;
+    const int rc0 = build_quad_tables(p, V.tile, V.depth, blocks, rec);
+    if (rc0 != AA_OK) return rc0;
+    t.bd = kQuadTrials;
+    t.nchan_pad = (p->nchan + 3) / 4 * 4;
+    t.max_row = 0;
+    t.blocks = blocks;
+    if (p->device >= 0) {
+        int rc = upload(&t.d_blocks, blocks);
+        if (rc == AA_OK) rc = upload(&t.d_offs, rec);
+        if (rc != AA_OK) return rc;
+    }
+    return AA_OK;
+}
+
 int prepare_mfma(const aa_plan_s* p, const DedispVariant& V, DedispTables& t) {
     std::vector<DmBlock> blocks;
     std::vector<int32_t> rsv;
@@ -312,7 +468,7 @@ int prepare_variant(aa_plan_s* p, int v) {
     if (V.layout >= 4) {
         DedispTables t;
         t.variant = v;
-        const int rc = prepare_mfma(p, V, t);
+        const int rc = V.layout == 7 ? prepare_quad(p, V, t) : prepare_mfma(p, V, t);
         if (rc != AA_OK) {
             free_tables(t);
             return rc;
