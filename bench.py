@@ -42,6 +42,11 @@ CU, CLOCK_GHZ, LANES = 256, 2.4, 64
 # int32 VALU adds: 256 CU x 64 lanes x 2.4 GHz = 39.3 T/s. The kernel adds bytes as
 # packed 16-bit pairs inside 32-bit adds, i.e. 2 byte-adds per lane operation.
 ALU_PEAK_TOPS = 2 * CU * LANES * CLOCK_GHZ / 1000.0   # 78.6 T byte-adds/s
+# LDS read bandwidth: 128 bytes per clock per CU (256 x 128 x 2.4 GHz = 78.6 TB/s). A
+# sum that reads each staged byte from LDS once per add is bound there at 1 byte/add.
+LDS_PEAK_TBS = CU * 128 * CLOCK_GHZ / 1000.0
+# v_sad_u8 adds four bytes per lane operation: 157 T byte-adds/s.
+SAD_PEAK_TOPS = 4 * CU * LANES * CLOCK_GHZ / 1000.0
 # Dense int8 matrix-core peak (v_mfma_i32_*_i8), TOP/s.
 I8_MFMA_PEAK_TOPS = 5000.0
 # HBM bytes per launch of the dedispersion kernel (FETCH_SIZE x 2.000 + WRITE_SIZE x
@@ -50,9 +55,8 @@ I8_MFMA_PEAK_TOPS = 5000.0
 # the kernel sources the counters were taken on: after any change to those sources the
 # entry no longer matches and the bench reports traffic as null.
 TRAFFIC_BYTES = {
-    ("survey_4096ch_1M", 12): (175.5e9 + 12.15e9, "f35a3ed52029e5c3"),
-    ("survey_4096ch_1M", 17): (279.1e9 + 12.15e9, "f35a3ed52029e5c3"),
-    ("survey_4096ch_1M", 20): (203.2e9 + 12.15e9, "f35a3ed52029e5c3"),
+    ("survey_4096ch_1M", 20): (202.85e9 + 12.14e9, "2dada2abdb5b3776"),
+    ("survey_4096ch_1M", 23): (422.71e9 + 12.14e9, "2dada2abdb5b3776"),
 }
 KERNEL_SOURCES = ("dedisp.hip", "tiling.cpp", "aa_internal.h", "xcd.h")
 # the part of aa_internal.h that the dedispersion kernels use: tiling constants, variant
@@ -631,6 +635,9 @@ def main():
                     "frac": achieved / I8_MFMA_PEAK_TOPS, "traffic": traffic, "per_launch_ops": adds,
                     "ms_per_launch": ms_dedisp, "alu_peak": ALU_PEAK_TOPS, "alu_frac": achieved / ALU_PEAK_TOPS,
                     "hbm_frac": (ndm * n_dd * 4 + nchan * w["nsamp"]) / (ms_dedisp * 1e-3) / (HBM_PEAK_GBS * 1e9)}
+    elif vinfo["layout"] == 7:
+        roofline = quad_roofline(adds, ms_dedisp)
+        roofline["traffic"] = traffic
     else:
         roofline = {"bound": "alu", "kernel": "dedisp_kernel", "achieved": achieved, "peak": ALU_PEAK_TOPS,
                     "unit": "TOP/s", "frac": achieved / ALU_PEAK_TOPS, "traffic": traffic,
@@ -657,15 +664,19 @@ def main():
         "candidates": int(h_count.item()),
     }
     if a.variant == "auto":
-        # the best variant without matrix cores (shift-and-add in LDS, layouts 0-3), from
-        # the same autotune pass (one timed launch each), priced against the VALU add peak
-        sa = [(m, v) for v, m in enumerate(ms) if m > 0 and variants[v]["layout"] in (0, 1, 2, 3)]
+        # the best variant without matrix cores (shift-and-add: layouts 0-3 in packed
+        # 16-bit adds, layout 7 with v_sad_u8 on staged channel quads), from the same
+        # autotune pass (one timed launch each)
+        sa = [(m, v) for v, m in enumerate(ms) if m > 0 and variants[v]["layout"] in (0, 1, 2, 3, 7)]
         if sa:
             m, v = min(sa)
-            ach = adds / (m * 1e-3) / 1e12
-            res["shift_and_add"] = {"variant": v, "ms_per_launch": m, "achieved": ach, "peak": ALU_PEAK_TOPS,
-                                    "unit": "TOP/s", "frac": ach / ALU_PEAK_TOPS, "bound": "alu",
-                                    "value_if_used": ndm * n_dd / ((m + ms_sps) * 1e-3)}
+            if variants[v]["layout"] == 7:
+                res["shift_and_add"] = quad_roofline(adds, m)
+            else:
+                ach = adds / (m * 1e-3) / 1e12
+                res["shift_and_add"] = {"bound": "alu", "achieved": ach, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
+                                        "frac": ach / ALU_PEAK_TOPS, "ms_per_launch": m}
+            res["shift_and_add"].update(variant=v, value_if_used=ndm * n_dd / ((m + ms_sps) * 1e-3))
     if not a.no_extras and not a.ndm and w["name"] == "survey_4096ch_1M":
         res["decimated"] = decimated_run(w, x, None, stream)
     if not a.no_cpu_baseline:
@@ -684,6 +695,17 @@ def main():
 
 
 SURVEY_RANGES = ([0, 512, 1024, 1536, 2048, 2432], [1, 2, 4, 8, 16, 32])
+
+
+def quad_roofline(adds, ms):
+    """Roofline of a quad shift-and-add launch: bound by LDS reads at one staged byte per
+    byte-add (the algorithmic LDS bytes of an LDS-staged sum), with the v_sad_u8 VALU
+    peak beside it."""
+    gbs = adds / (ms * 1e-3) / 1e9
+    return {"bound": "lds", "kernel": "dedisp_kernel (quad shift-and-add, v_sad_u8)", "achieved": gbs,
+            "peak": LDS_PEAK_TBS * 1000.0, "unit": "GB/s", "frac": gbs / (LDS_PEAK_TBS * 1000.0),
+            "per_launch_bytes": adds, "ms_per_launch": ms, "valu_peak_tops": SAD_PEAK_TOPS,
+            "valu_frac": gbs / 1000.0 / SAD_PEAK_TOPS, "alu_frac": gbs / 1000.0 / ALU_PEAK_TOPS}
 
 
 def decimated_run(w, x, variant, stream, steps=5):

@@ -922,8 +922,8 @@ typedef void (*DedispBatchFn)(const DedispArgs*, const int64_t*, int, int64_t, u
     K<4, 4, 1>, K<2, 8, 1>, K<4, 8, 1>, K<2, 16, 1>, K<2, 8, 0>, K<4, 4, 0>, K<2, 8, 3>, K<4, 4, 3>, \
         K<2, 8, 2>, K<4, 8, 2>, K<4, 4, 2>, K<4, 8, 4, 1024, 3>, K<2, 16, 4, 1024, 3>, K<2, 16, 4, 768, 7>, \
         K<4, 8, 4, 512, 3, 31, 4>, K<2, 16, 4, 512, 3, 31, 8>, K<4, 8, 4, 480, 4, 31, 4>, K<2, 16, 5, 864, 3, 63>, \
-        K<2, 16, 4, 960, 4, 63>, K<2, 16, 4, 896, 5, 63>, K<2, 16, 6, 864, 3, 63>, K<4, 4, 7, 1024, 8, 0, 2>, \
-        K<2, 8, 7, 1024, 4, 0, 4>, K<4, 8, 7, 2048, 8, 0, 2>, K<2, 8, 7, 1024, 6, 0, 2>
+        K<2, 16, 4, 960, 4, 63>, K<2, 16, 4, 896, 5, 63>, K<2, 16, 6, 864, 3, 63>, K<2, 4, 7, 512, 4, 0, 4>, \
+        K<2, 8, 7, 1024, 4, 0, 4>, K<1, 16, 7, 1024, 2, 0, 8>, K<1, 8, 7, 512, 2, 0, 8>
 const DedispFn kKernels[kNumDedispVariants] = {AA_VARIANTS(dedisp_kernel)};
 const DedispBatchFn kBatchKernels[kNumDedispVariants] = {AA_VARIANTS(dedisp_batch_kernel)};
 #undef AA_VARIANTS

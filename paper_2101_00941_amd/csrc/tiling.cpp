@@ -40,10 +40,10 @@ const DedispVariant kDedispVariants[kNumDedispVariants] = {
     {20, 16, 2, mfma_lds_bytes(864, 3, 63, 8), 6, 864, 3, 63},  // 1024 threads, 4 tiles per wave
     // shift-and-add with v_sad_u8 on channel quads staged per residual pattern, 32 trials
     // per block; tile = 64 * waves * samples per lane, depth = staging chunks per step
-    {21, 4, 8, quad_lds_bytes(32), 7, 1024, 32, 0},   // 256 threads, 4 samples per lane
+    {21, 4, 8, quad_lds_bytes(16), 7, 512, 16, 0},    // 256 threads, 2 samples per lane
     {22, 8, 4, quad_lds_bytes(32), 7, 1024, 32, 0},   // 512 threads, 2 samples per lane
-    {23, 8, 4, quad_lds_bytes(64), 7, 2048, 64, 0},   // 512 threads, 4 samples per lane
-    {24, 8, 4, quad_lds_bytes(48), 7, 1024, 48, 0},   // 512 threads, 2 samples per lane
+    {23, 16, 2, quad_lds_bytes(32), 7, 1024, 32, 0},  // 1024 threads, 1 sample per lane
+    {24, 8, 4, quad_lds_bytes(16), 7, 512, 16, 0},    // 512 threads, 1 sample per lane
 };
 
 void free_tables(DedispTables& t) {

@@ -67,14 +67,15 @@ def test_batch_equals_plain_per_beam(beams, static, work_mb):
         assert all(int(c["beam"]) == i for c in cands[i])
 
 
-@pytest.mark.parametrize("variant", [12, 17, 20, 14, 16])
+@pytest.mark.parametrize("variant", [12, 17, 20, 14, 16, 21, 22, 23, 24])
 @pytest.mark.parametrize("work_mb", [512, 40])
-def test_batch_matrix_core_variants_match_oracle(beams, want, variant, work_mb):
+def test_batch_matrix_core_and_quad_variants_match_oracle(beams, want, variant, work_mb):
     """The persistent matrix-core kernels (one step shape, the mixed shape, and the
-    two-work-group-per-CU variants whose batch kernels spill registers) against the
-    oracle, every beam, with one group and with several."""
+    two-work-group-per-CU variants whose batch kernels spill registers) and the quad
+    shift-and-add kernels (whose batch kernels spill too) against the oracle, every
+    beam, with one group and with several."""
     from paper_2101_00941_amd import batch_run, candidates_as_tuples
-    say(f"batch matrix-core variant {variant} work={work_mb} MB")
+    say(f"batch variant {variant} work={work_mb} MB")
     cands, counts, info = batch_run([(b["plan"], b["dev"], b["nsamp"]) for b in beams], variant=variant,
                                     work_bytes=work_mb << 20, cap=4096)
     assert info["variant"] == variant and info["items"] > 0
