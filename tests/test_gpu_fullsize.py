@@ -6,8 +6,8 @@ The whole plane (3000 x 1,012,255 int32, 12 GB) is beyond the oracle, so the
 oracle checks sampled outputs, each computed on its own:
   * dedispersion: random (trial, sample) pairs, every trial at the first and last
     samples and at a random one, and full 32768-sample runs of a few trials, for
-    the autotuned variant, every matrix-core variant and one variant of each other
-    kernel family;
+    the autotuned variant, every matrix-core and quad shift-and-add variant and one
+    variant of each other kernel family;
   * candidates (plain and per-range decimated): every 100th trial and the two trials on each side of every
     injected pulse's DM (127 rows, chosen from the signal model), over the full
     time range. The oracle dedisperses each of those rows and its neighbours over
@@ -85,9 +85,10 @@ def test_survey_dedisp_sampled(survey):
     say(f"  autotune ms per variant {['%.1f' % m for m in ms]} -> variant {plan.variant}")
     chosen = plan.variant
     _check_plane(sv, dd, rng)
-    # every matrix-core variant (any of them can be the autotuner's pick), and the first
-    # variant of each other layout
-    check = {v for v, info in enumerate(Plan.variants()) if info["layout"] in (4, 5, 6)}
+    # every matrix-core and quad variant (any of them can be the autotuner's pick, and the
+    # quad variants differ in tile, waves and samples per lane), and the first variant of
+    # each other layout
+    check = {v for v, info in enumerate(Plan.variants()) if info["layout"] in (4, 5, 6, 7)}
     layouts = {}
     for v, info in enumerate(Plan.variants()):
         layouts.setdefault(info["layout"], v)
