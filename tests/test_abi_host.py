@@ -168,3 +168,25 @@ def test_plain_c_caller(tmp_path):
                     f"-Wl,-rpath,{libdir}", "-o", str(exe), "-lm"], check=True)
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stdout + r.stderr
+
+
+def test_quad_variants_refuse_wide_residuals(aa):
+    """Shifts within one quad of channels that differ by more than 1023 samples (10 MHz
+    channels near 400 MHz, DM 100, 1 us sampling: about 4e5 samples): every quad
+    shift-and-add variant refuses the plan with AA_EINVAL and says why, and the other
+    kernel families still prepare their tables (host-only plan: tables only)."""
+    from paper_2101_00941_amd import AAError, Plan
+    p = Plan(8, 1 << 26, 400.0, 10.0, 1e-6, [0.0, 100.0], [1], 6.0, host_only=True)
+    s = p.shifts().astype(np.int64)
+    assert s[1, 3] - s[1, 0] > 1023
+    variants = Plan.variants()
+    quads = [v for v, i in enumerate(variants) if i["layout"] == 7]
+    assert len(quads) >= 1
+    for v in quads:
+        with pytest.raises(AAError) as e:
+            p.set_variant(v)
+        assert e.value.code == aa.AA_EINVAL
+        assert b"1023" in aa.lib().aa_last_error()
+    for v in (1, 12, 20):
+        p.set_variant(v)
+        assert p.variant == v
