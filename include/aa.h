@@ -117,7 +117,8 @@ void aa_plan_destroy(aa_plan_t plan);
  * n_in:  valid samples per row. maxshift + 1 <= n_in <= in_pitch.
  * d_out: int32 [ndm][out_pitch], out_pitch >= n_in - maxshift, 16-byte aligned rows.
  *        Columns >= n_in - maxshift are not written.
- * Errors: AA_EINVAL on a host-only plan, bad sizes or misaligned pointers.
+ * Errors: AA_EINVAL on a host-only plan, bad sizes or misaligned pointers, or
+ * in_pitch above 2^28 bytes with a quad variant (layout 7) in use.
  * AA_EHIP if the launch fails.
  */
 int aa_dedisperse(aa_plan_t plan, const uint8_t* d_in, int64_t in_pitch, int64_t n_in,
@@ -138,7 +139,9 @@ int aa_dedisperse(aa_plan_t plan, const uint8_t* d_in, int64_t in_pitch, int64_t
  *   aa_autotune(...)              time every variant on the caller's buffers (reps runs
  *                                 each, HIP events on `stream`), select the fastest,
  *                                 and write the per-variant mean ms to ms_out
- *                                 [aa_variant_count()]. If AA_TUNE_CACHE names a file,
+ *                                 [aa_variant_count()]; variants that cannot take the
+ *                                 input (quad variants with in_pitch above 2^28) are
+ *                                 skipped (-1). If AA_TUNE_CACHE names a file,
  *                                 the choice is read from and written to that JSON
  *                                 cache, keyed by device arch and plan shape.
  * d_out receives the dedispersed plane of the last run.

@@ -105,17 +105,26 @@ constexpr int mfma_lds_bytes(int tile, int depth, int max_tiles, int cps = 4) {
 //   32                chunks of step e (0 for e = nq)
 //   64 + 4 j + i      row offset of channel i for chunk j of step e: lo_p + r_i + 256 c,
 //                     c = j - cb_p (relative to the time tile; its low 2 bits are the
-//                     byte phase of the row within a dword)
+//                     byte phase of the row within a dword); kQuadNoRow for channels
+//                     past nchan
 // so that one record serves the sums of step e - 1 and the staging of step e.
-// Channels past nchan stage zero bytes and have r = 0.
+// Channels past nchan have r = 0 and stage zero bytes: their loads start at or beyond
+// 2^30, outside the quad's load range (at most four row pitches of at most 2^28 bytes).
 constexpr int kQuadTrials = 32;
 constexpr int kQuadMaxPat = 8;
 constexpr int quad_rec_dwords(int chunks) { return (64 + 4 * chunks + 63) / 64 * 64; }
 constexpr int kQuadMaxResidual = 1023;
 constexpr int kQuadMaxChunks = 64;   // trial offsets stay below 64 KB
+constexpr int32_t kQuadNoRow = int32_t{1} << 30;
+constexpr int64_t kQuadMaxPitch = int64_t{1} << 28;   // four row pitches stay below kQuadNoRow
 constexpr int quad_lds_bytes(int chunks) { return 2 * chunks * 1024; }
 
 extern const DedispVariant kDedispVariants[kNumDedispVariants];
+// Input row pitches a variant can take (the quad variants address four rows from one
+// 32-bit range).
+inline bool variant_takes_pitch(int variant, int64_t in_pitch) {
+    return kDedispVariants[variant].layout != 7 || in_pitch <= kQuadMaxPitch;
+}
 constexpr int kDefaultDedispVariant = 12;   // i8 matrix cores, 16 waves
 
 // Single-pulse-search tiling: a work-group covers kSpsRows DM rows and kSpsTile starts.

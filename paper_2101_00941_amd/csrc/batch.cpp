@@ -74,8 +74,8 @@ extern "C" int aa_batch_run(const aa_batch_beam_t* beams, int32_t nbeams, int32_
     }
     if (variant >= kNumDedispVariants) return fail(AA_EINVAL, "aa_batch_run: unknown variant");
     for (int i = 0; i < nbeams; ++i)
-        if (kDedispVariants[variant].layout == 7 && ((beams[i].n_in + 15) & ~int64_t{15}) > (int64_t{1} << 30))
-            return fail(AA_EINVAL, "aa_batch_run: the quad variants take rows of at most 2^30 samples");
+        if (!variant_takes_pitch(variant, beams[i].in_pitch))
+            return fail(AA_EINVAL, "aa_batch_run: the quad variants take row pitches of at most 2^28 bytes");
     for (int i = 0; i < nbeams; ++i) {
         const int rc = prepare_variant(beams[i].plan, variant);
         if (rc != AA_OK) return rc;

@@ -712,6 +712,85 @@ __device__ __forceinline__ void dedisp_mfma_tile(const DedispArgs& A, int blk, i
 // so staging a chunk costs four scalar ops. Each channel row has its own buffer
 // resource spanning [0, n_in16) (empty for channels past nchan): the range check of raw
 // buffer loads returns zero for the dwords outside it.
+// Sums of eight trials, one dword each (one sample per lane): the eight window addresses
+// (lane dword plus the u16 halves of four record pairs), the eight LDS reads in flight
+// together, then the v_sad_u8 adds as the reads land. The block waits for its own reads
+// before it ends; the reads are the youngest LDS/scalar-memory operations in flight, so
+// the partial waits are exact or conservative.
+__device__ __forceinline__ void sad_group8(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3, uint32_t& c4,
+                                           uint32_t& c5, uint32_t& c6, uint32_t& c7, uint32_t base, uint32_t p0,
+                                           uint32_t p1, uint32_t p2, uint32_t p3) {
+    uint32_t a0, a1, a2, a3, a4, a5, a6, a7;
+    asm volatile(
+        "v_mad_u32_u16 %[a0], %[p0], 1, %[b]\n\t"
+        "v_mad_u32_u16 %[a1], %[p0], 1, %[b] op_sel:[1,0,0,0]\n\t"
+        "v_mad_u32_u16 %[a2], %[p1], 1, %[b]\n\t"
+        "v_mad_u32_u16 %[a3], %[p1], 1, %[b] op_sel:[1,0,0,0]\n\t"
+        "v_mad_u32_u16 %[a4], %[p2], 1, %[b]\n\t"
+        "v_mad_u32_u16 %[a5], %[p2], 1, %[b] op_sel:[1,0,0,0]\n\t"
+        "v_mad_u32_u16 %[a6], %[p3], 1, %[b]\n\t"
+        "v_mad_u32_u16 %[a7], %[p3], 1, %[b] op_sel:[1,0,0,0]\n\t"
+        "ds_read_b32 %[a0], %[a0]\n\t"
+        "ds_read_b32 %[a1], %[a1]\n\t"
+        "ds_read_b32 %[a2], %[a2]\n\t"
+        "ds_read_b32 %[a3], %[a3]\n\t"
+        "ds_read_b32 %[a4], %[a4]\n\t"
+        "ds_read_b32 %[a5], %[a5]\n\t"
+        "ds_read_b32 %[a6], %[a6]\n\t"
+        "ds_read_b32 %[a7], %[a7]\n\t"
+        "s_waitcnt lgkmcnt(7)\n\t"
+        "v_sad_u8 %[c0], %[a0], 0, %[c0]\n\t"
+        "s_waitcnt lgkmcnt(6)\n\t"
+        "v_sad_u8 %[c1], %[a1], 0, %[c1]\n\t"
+        "s_waitcnt lgkmcnt(5)\n\t"
+        "v_sad_u8 %[c2], %[a2], 0, %[c2]\n\t"
+        "s_waitcnt lgkmcnt(4)\n\t"
+        "v_sad_u8 %[c3], %[a3], 0, %[c3]\n\t"
+        "s_waitcnt lgkmcnt(3)\n\t"
+        "v_sad_u8 %[c4], %[a4], 0, %[c4]\n\t"
+        "s_waitcnt lgkmcnt(2)\n\t"
+        "v_sad_u8 %[c5], %[a5], 0, %[c5]\n\t"
+        "s_waitcnt lgkmcnt(1)\n\t"
+        "v_sad_u8 %[c6], %[a6], 0, %[c6]\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_sad_u8 %[c7], %[a7], 0, %[c7]"
+        : [c0] "+v"(c0), [c1] "+v"(c1), [c2] "+v"(c2), [c3] "+v"(c3), [c4] "+v"(c4), [c5] "+v"(c5), [c6] "+v"(c6),
+          [c7] "+v"(c7), [a0] "=&v"(a0), [a1] "=&v"(a1), [a2] "=&v"(a2), [a3] "=&v"(a3), [a4] "=&v"(a4),
+          [a5] "=&v"(a5), [a6] "=&v"(a6), [a7] "=&v"(a7)
+        : [b] "v"(base), [p0] "s"(p0), [p1] "s"(p1), [p2] "s"(p2), [p3] "s"(p3));
+}
+
+// Reads of eight trials, two dwords each (two samples per lane, 64 W dwords apart, one
+// ds_read2st64_b32): addresses as in sad_group8, the eight reads in flight together,
+// and a wait for them before the block ends.
+template <int W>
+__device__ __forceinline__ void read_group8_st64(uint64_t (&r)[8], uint32_t base, uint32_t p0, uint32_t p1,
+                                                 uint32_t p2, uint32_t p3) {
+    uint32_t a0, a1, a2, a3, a4, a5, a6, a7;
+    asm volatile(
+        "v_mad_u32_u16 %[a0], %[p0], 1, %[b]\n\t"
+        "v_mad_u32_u16 %[a1], %[p0], 1, %[b] op_sel:[1,0,0,0]\n\t"
+        "v_mad_u32_u16 %[a2], %[p1], 1, %[b]\n\t"
+        "v_mad_u32_u16 %[a3], %[p1], 1, %[b] op_sel:[1,0,0,0]\n\t"
+        "v_mad_u32_u16 %[a4], %[p2], 1, %[b]\n\t"
+        "v_mad_u32_u16 %[a5], %[p2], 1, %[b] op_sel:[1,0,0,0]\n\t"
+        "v_mad_u32_u16 %[a6], %[p3], 1, %[b]\n\t"
+        "v_mad_u32_u16 %[a7], %[p3], 1, %[b] op_sel:[1,0,0,0]\n\t"
+        "ds_read2st64_b32 %[r0], %[a0] offset1:%[st]\n\t"
+        "ds_read2st64_b32 %[r1], %[a1] offset1:%[st]\n\t"
+        "ds_read2st64_b32 %[r2], %[a2] offset1:%[st]\n\t"
+        "ds_read2st64_b32 %[r3], %[a3] offset1:%[st]\n\t"
+        "ds_read2st64_b32 %[r4], %[a4] offset1:%[st]\n\t"
+        "ds_read2st64_b32 %[r5], %[a5] offset1:%[st]\n\t"
+        "ds_read2st64_b32 %[r6], %[a6] offset1:%[st]\n\t"
+        "ds_read2st64_b32 %[r7], %[a7] offset1:%[st]\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : [r0] "=&v"(r[0]), [r1] "=&v"(r[1]), [r2] "=&v"(r[2]), [r3] "=&v"(r[3]), [r4] "=&v"(r[4]),
+          [r5] "=&v"(r[5]), [r6] "=&v"(r[6]), [r7] "=&v"(r[7]), [a0] "=&v"(a0), [a1] "=&v"(a1), [a2] "=&v"(a2),
+          [a3] "=&v"(a3), [a4] "=&v"(a4), [a5] "=&v"(a5), [a6] "=&v"(a6), [a7] "=&v"(a7)
+        : [b] "v"(base), [p0] "s"(p0), [p1] "s"(p1), [p2] "s"(p2), [p3] "s"(p3), [st] "n"(W));
+}
+
 __device__ __forceinline__ void lds_step_barrier() {
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     __builtin_amdgcn_s_barrier();
@@ -728,7 +807,7 @@ __device__ __forceinline__ void dedisp_quad_tile(const DedispArgs& A, int blk, i
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const DmBlock b = A.blocks[blk];
-    const int nq = A.nchan_pad >> 2, nchan = A.nchan, count = b.count;
+    const int nq = A.nchan_pad >> 2, count = b.count;
     const int64_t pitch = A.in_pitch;
     const int32_t n_in16 = static_cast<int32_t>(A.n_in16);
     // records are read-only for the launch: the constant address space makes their
@@ -763,23 +842,37 @@ __device__ __forceinline__ void dedisp_quad_tile(const DedispArgs& A, int blk, i
             for (int i = 0; i < 4; ++i) co[m][i] = E[64 + 4 * (wave + W * m) + i];
     };
 
-    auto issue = [&](int q) {
-        __amdgpu_buffer_rsrc_t rs[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            rs[i] = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(A.in + static_cast<int64_t>(4 * q + i) * pitch),
-                                                      0, 4 * q + i < nchan ? n_in16 : 0, kRawBufferFlags);
+    // One buffer resource per quad, based at its first row; row i is reached through the
+    // scalar offset i * pitch, which the range check counts. The range ends where the
+    // quad's last existing row ends (n_in16 past its start): a row's loads past its own
+    // n_in16 read the next row's bytes, which only reach samples at or past n_out (never
+    // stored), and nothing past the last row is read. Rows past nchan carry the row
+    // offset kQuadNoRow, at or beyond every range (pitches are at most 2^28), and read zero.
+    const uint32_t soff[4] = {0u, static_cast<uint32_t>(pitch), static_cast<uint32_t>(2 * pitch),
+                              static_cast<uint32_t>(3 * pitch)};
+    const int full_quads = A.nchan >> 2;
+    const int32_t range_full = static_cast<int32_t>(3 * pitch) + n_in16;
+    const int32_t range_last = static_cast<int32_t>((A.nchan - 1 - 4 * full_quads) * pitch) + n_in16;
+    const uint8_t* quad_row = A.in;
+    int next_q = 0;
+    auto issue = [&]() {
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<uint8_t*>(quad_row), 0, next_q < full_quads ? range_full : range_last, kRawBufferFlags);
 #pragma unroll
         for (int m = 0; m < CPW; ++m) {
             if (wave + W * m < nch) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const uint32_t voff = lane_t0 + static_cast<uint32_t>(co[m][i] & ~3);
-                    sw[m][i][0] = static_cast<uint32_t>(__builtin_amdgcn_raw_buffer_load_b32(rs[i], voff, 0, 0));
-                    sw[m][i][1] = static_cast<uint32_t>(__builtin_amdgcn_raw_buffer_load_b32(rs[i], voff + 4u, 0, 0));
+                    // the lane's part in the vector offset, the row's in the scalar one
+                    const uint32_t so = soff[i] + static_cast<uint32_t>(co[m][i] & ~3);
+                    const auto w2 = __builtin_amdgcn_raw_buffer_load_b64(rs, lane_t0, so, 0);
+                    sw[m][i][0] = w2[0];
+                    sw[m][i][1] = w2[1];
                 }
             }
         }
+        quad_row += 4 * pitch;
+        ++next_q;
     };
 
     auto write = [&](int buf) {
@@ -802,25 +895,35 @@ __device__ __forceinline__ void dedisp_quad_tile(const DedispArgs& A, int blk, i
         }
     };
 
+    typedef const __attribute__((address_space(3))) uint32_t* lds_u32;
+
     load_rec(R);
-    issue(0);
+    issue();
     write(0);
     load_rec(R + RD);
     lds_step_barrier();
     for (int k = 0; k < nq; ++k) {
         const bool more = k + 1 < nq;
-        if (more) issue(k + 1);
-        const uint8_t* y = lds + (k & 1) * BUFB + 4 * tid;
+        if (more) issue();
+        const uint32_t y = static_cast<uint32_t>(reinterpret_cast<uintptr_t>((lds_u32)(const void*)lds)) +
+                           static_cast<uint32_t>((k & 1) * BUFB + 4 * tid);
         // trials in groups of 8; a block's absent trials (short blocks) are skipped per group
 #pragma unroll
         for (int g = 0; g < NTR / 8; ++g) {
             if (8 * g < count) {
+                if constexpr (J == 1) {
+                    sad_group8(acc[8 * g][0], acc[8 * g + 1][0], acc[8 * g + 2][0], acc[8 * g + 3][0], acc[8 * g + 4][0],
+                               acc[8 * g + 5][0], acc[8 * g + 6][0], acc[8 * g + 7][0], y, toff[4 * g], toff[4 * g + 1],
+                               toff[4 * g + 2], toff[4 * g + 3]);
+                } else {
+                    static_assert(J == 2, "one or two dwords per lane");
+                    uint64_t r[8];
+                    read_group8_st64<W>(r, y, toff[4 * g], toff[4 * g + 1], toff[4 * g + 2], toff[4 * g + 3]);
 #pragma unroll
-                for (int d = 8 * g; d < 8 * g + 8; ++d) {
-                    const uint32_t off = (d & 1) ? toff[d >> 1] >> 16 : toff[d >> 1] & 0xFFFFu;
-                    const uint32_t* yd = reinterpret_cast<const uint32_t*>(y + off);
-#pragma unroll
-                    for (int j = 0; j < J; ++j) acc[d][j] = __builtin_amdgcn_sad_u8(yd[NT * j], 0u, acc[d][j]);
+                    for (int i = 0; i < 8; ++i) {
+                        acc[8 * g + i][0] = __builtin_amdgcn_sad_u8(static_cast<uint32_t>(r[i]), 0u, acc[8 * g + i][0]);
+                        acc[8 * g + i][1] = __builtin_amdgcn_sad_u8(static_cast<uint32_t>(r[i] >> 32), 0u, acc[8 * g + i][1]);
+                    }
                 }
             }
         }
@@ -963,8 +1066,8 @@ int launch_dedisperse(const aa_plan_s* p, int variant, const uint8_t* d_in, int6
     if (T.variant != variant || !T.d_offs) return fail(AA_EINVAL, "aa_dedisperse: variant tables not prepared");
     const DedispVariant& V = kDedispVariants[variant];
     const DedispArgs a = dedisp_args(p, variant, d_in, in_pitch, n_in, d_out, out_pitch);
-    if (V.layout == 7 && a.n_in16 > (int64_t{1} << 30))
-        return fail(AA_EINVAL, "aa_dedisperse: the quad variants take rows of at most 2^30 samples");
+    if (!variant_takes_pitch(variant, in_pitch))
+        return fail(AA_EINVAL, "aa_dedisperse: the quad variants take row pitches of at most 2^28 bytes");
     const int64_t grid = a.ntile * a.nblk;
     if (grid > 0x7fffffff) return fail(AA_EINVAL, "aa_dedisperse: too many tiles for one launch");
     const size_t lds = V.layout >= 4 ? static_cast<size_t>(V.lds_bytes) : static_cast<size_t>(2 * kChanPerPass) * T.max_row;

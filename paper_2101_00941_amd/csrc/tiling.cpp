@@ -405,6 +405,8 @@ int build_quad_tables(const aa_plan_s* p, int tile, int chunks, std::vector<DmBl
                     C[1] = static_cast<int32_t>(Q.lo + Q.r1 + 256 * c);
                     C[2] = static_cast<int32_t>(Q.lo + Q.r2 + 256 * c);
                     C[3] = static_cast<int32_t>(Q.lo + Q.r3 + 256 * c);
+                    for (int i = 1; i < 4; ++i)
+                        if (4 * q + i >= nchan) C[i] = kQuadNoRow;
                 }
                 nch += n;
             }

@@ -119,7 +119,7 @@ extern "C" int aa_autotune(aa_plan_t p, const uint8_t* d_in, int64_t in_pitch, i
     int rc = AA_OK;
     for (int v = 0; v < kNumDedispVariants; ++v) {
         float ms = -1.0f;
-        if (prepare_variant(p, v) == AA_OK) {
+        if (variant_takes_pitch(v, in_pitch) && prepare_variant(p, v) == AA_OK) {
             rc = launch_dedisperse(p, v, d_in, in_pitch, n_in, d_out, out_pitch, stream);  // warm-up
             if (rc != AA_OK) break;
             (void)hipEventRecord(e0, stream);

@@ -3,10 +3,12 @@
 // D[d][t] = sum_c X[c][t + s[d][c]] computed directly. The model stages each step the
 // way the kernel does (64-unit chunks at recorded row offsets, two aligned dwords per
 // channel and unit, byte alignment, 4x4 transpose, whole chunks written), then sums every
-// trial's dwords at its recorded offset. Loads follow the kernel's per-row buffer
-// ranges (dwords past n_in16, and rows past nchan, read as zero); the model also checks
-// that every LDS access stays inside the step buffer.
+// trial's dwords at its recorded offset. Loads follow the kernel's per-quad buffer range
+// (a row's loads past its n_in16 read the next row's bytes, and the pitch padding, which
+// only samples past n_out see; rows past nchan read zero and are never touched); the
+// model also checks that every LDS access stays inside the step buffer.
 // Host-only plan: no GPU needed. Usage: quad_tables_check TILE CHUNKS
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -83,13 +85,22 @@ static int run_case(int nchan, int nsamp, double ftop, double foff, double tsamp
                         for (int i = 0; i < 4; ++i) {
                             const int c = 4 * q + i;
                             const int32_t o = P[64 + 4 * j + i];
-                            // per-row range [0, n_in16), empty past nchan; dword-aligned loads
+                            if (c >= nchan && o != kQuadNoRow) { printf("a row past nchan without the no-row offset\n"); return 1; }
+                            // one range per quad from its first row to n_in16 past the start of
+                            // its last existing row; row i at i * pitch within it; dword loads
                             const int64_t a = t0 + (o & ~3) + 4 * lane;
+                            const int64_t last = std::min(3, nchan - 1 - 4 * q);
+                            const int64_t range = last * pitch + n_in16;
                             uint32_t w[2] = {0, 0};
                             for (int h = 0; h < 2; ++h) {
                                 const int64_t ah = a + 4 * h;
                                 if (ah < 0) { ++oob; continue; }
-                                if (c < nchan && ah + 4 <= n_in16) memcpy(&w[h], &x[c * pitch + ah], 4);
+                                const int64_t at = i * pitch + ah;   // offset from the quad's first row
+                                if (at + 4 <= range) {
+                                    if (c >= nchan) { printf("a load of a row past nchan\n"); return 1; }
+                                    if ((size_t)(4 * q) * pitch + at + 4 > x.size()) { printf("a load past the input\n"); return 1; }
+                                    memcpy(&w[h], &x[(size_t)(4 * q) * pitch + at], 4);
+                                }
                             }
                             v[i] = (uint32_t)((((uint64_t)w[1] << 32) | w[0]) >> (8 * (o & 3)));
                         }
