@@ -233,3 +233,37 @@ def test_extreme_widths_match_oracle(nchan, widths, thr):
         if with_best:
             assert np.array_equal(r["best"], want["best"])
     assert len(want["candidates"]) > 0
+
+
+def test_quad_variants_refuse_wide_pitches_and_autotune_skips_them():
+    """The quad variants address a quad's four rows from one 32-bit buffer range, so they
+    take row pitches of at most 2^28 bytes: with a wider pitch aa_dedisperse refuses them
+    before any launch, and aa_autotune leaves them out (-1) and picks among the others,
+    whose result stays exact."""
+    import torch
+    from paper_2101_00941_amd import Plan
+    from paper_2101_00941_amd._native import AAError
+    nchan, nsamp = 7, 6000
+    pitch = (1 << 28) + 256
+    rng = np.random.default_rng(11)
+    x = rng.integers(0, 256, (nchan, nsamp), dtype=np.uint8)
+    p = _plan(nchan, nsamp, 1500.0, 3.0, 64e-6, [0.0, 10.0, 20.0, 40.0], [1], 1e9)
+    say(f"{nchan} ch x {nsamp}, pitch {pitch}")
+    xd = torch.full((nchan, pitch), 255, dtype=torch.uint8, device="cuda")
+    xd[:, :nsamp] = torch.from_numpy(x).cuda()
+    quad = [v for v, info in enumerate(Plan.variants()) if info["layout"] == 7]
+    assert quad
+    p.set_variant(quad[0])
+    with pytest.raises(AAError) as err:
+        p.dedisperse(xd, n_in=nsamp)
+    assert err.value.code == -1 and "2^28" in str(err.value)   # AA_EINVAL
+    ms = p.autotune(xd, n_in=nsamp, reps=1)
+    assert all(ms[v] == -1.0 for v in quad)
+    assert all(m > 0 for v, m in enumerate(ms) if v not in quad)
+    assert p.variant not in quad
+    want = oracle.dedisperse(x, p.shifts().astype(np.int64), nsamp)
+    D = p.dedisperse(xd, n_in=nsamp)
+    torch.cuda.synchronize()
+    assert np.array_equal(D[:, :want.shape[1]].cpu().numpy().astype(np.int64), want)
+    del xd
+    torch.cuda.empty_cache()
