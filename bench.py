@@ -467,11 +467,13 @@ def batched(a):
         c, cnt, _ = plan.single_pulse(dd, cap=cap)
         plain_counts.append(cnt)
         plain_cands.append(c)
+    # both paths hand the candidate lists to the host inside their timed region
+    plain_lists = [candidates_to_numpy(plain_cands[i], plain_counts[i], cap) for i in range(len(beams))]
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t
     same = True
     for i in range(len(beams)):
-        pc = candidates_as_tuples(candidates_to_numpy(plain_cands[i], plain_counts[i], cap))
+        pc = candidates_as_tuples(plain_lists[i])
         same &= int(plain_counts[i].item()) == int(counts[i]) and pc == candidates_as_tuples(cands[i])
     log(f"[bench] plain loop: {t_plain * 1e3:.1f} ms; identical results: {same}")
     return dict(workload="batched_64beams", beams=len(beams), input_gb=in_gb, dm_trial_samples=work_units,

@@ -436,11 +436,11 @@ def batch_run(beams, variant=-1, work=None, work_bytes=None, cap=1 << 16, static
     N.check(N.lib().aa_batch_run(arr, n, int(variant), _ptr(work), work.numel(), _ptr(cand), int(cap), _ptr(count),
                                  N.AA_BATCH_STATIC if static else 0, C.byref(info), _stream_handle(stream)))
     counts = count.cpu().numpy().astype(np.int64)
-    raw = cand.cpu().numpy()
     out = []
-    for i in range(n):
+    for i in range(n):   # only the filled part of each beam's slot comes to the host
         k = int(min(counts[i], cap))
-        out.append(raw[i * cap * 24:(i * cap + k) * 24].view(N.CANDIDATE_DTYPE).copy())
+        raw = cand[i * cap * 24:(i * cap + k) * 24].cpu().numpy()
+        out.append(raw.view(N.CANDIDATE_DTYPE).copy())
     d = {k: getattr(info, k) for k, _ in N.BatchInfo._fields_}
     d["tune_ms"] = [float(v) for v in info.tune_ms][:N.lib().aa_variant_count()]
     return out, counts, d

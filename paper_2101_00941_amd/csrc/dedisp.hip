@@ -28,6 +28,22 @@
 namespace aa {
 namespace {
 
+// A DM block's table entry, read through the constant address space: it is the same in
+// every lane and read-only for the launch, so its loads are scalar even where the table
+// pointer comes from memory (the persistent batch kernel reads it from the beam's
+// argument block).
+__device__ __forceinline__ DmBlock load_block(const DmBlock* blocks, int blk) {
+    static_assert(sizeof(DmBlock) % 4 == 0, "a DM block entry is whole dwords");
+    typedef const __attribute__((address_space(4))) int32_t* word_ptr;
+    const word_ptr p = (word_ptr)(const void*)(blocks + blk);
+    int32_t w[sizeof(DmBlock) / 4];
+#pragma unroll
+    for (int i = 0; i < static_cast<int>(sizeof(DmBlock) / 4); ++i) w[i] = p[i];
+    DmBlock b;
+    __builtin_memcpy(&b, w, sizeof(b));
+    return b;
+}
+
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) void lds_void;
 
@@ -130,7 +146,7 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs& A, int blk, int64_
     const int32_t* __restrict__ offs = A.offs;
     const int nchan = A.nchan, nchan_pad = A.nchan_pad, row = A.row;
     int32_t* __restrict__ out = A.out;
-    const DmBlock b = A.blocks[blk];
+    const DmBlock b = load_block(A.blocks, blk);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int32_t* bbase = base + static_cast<int64_t>(blk) * nchan_pad;
@@ -612,7 +628,7 @@ __device__ __forceinline__ void dedisp_mfma_tile(const DedispArgs& A, int blk, i
     cx.t0 = t0;
     cx.last16 = A.n_in16 - 16;
     cx.K = A.nchan_pad / CPS;
-    cx.recg = reinterpret_cast<const uint8_t*>(A.offs) + static_cast<int64_t>(A.blocks[blk].rec256) * 256;
+    cx.recg = reinterpret_cast<const uint8_t*>(A.offs) + static_cast<int64_t>(load_block(A.blocks, blk).rec256) * 256;
     const int tid = threadIdx.x;
     cx.wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     cx.lane = tid & 63;
@@ -625,7 +641,7 @@ __device__ __forceinline__ void dedisp_mfma_tile(const DedispArgs& A, int blk, i
     cx.ps = cx.wave == 0 ? 2 : (cx.wave < L::SW ? 1 : 0);  // loads this wave issues per step
     const int32_t* rsv = A.base + static_cast<int64_t>(blk) * A.nchan_pad;
     {
-        const DmBlock bk = A.blocks[blk];
+        const DmBlock bk = load_block(A.blocks, blk);
         cx.interior = t0 + bk.rs_lo >= 0 && t0 + bk.rs_hi + L::ROW <= A.n_in16;
     }
     const int64_t step_bytes = CPS * A.in_pitch;
@@ -675,7 +691,7 @@ __device__ __forceinline__ void dedisp_mfma_tile(const DedispArgs& A, int blk, i
     asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
     __syncthreads();
 
-    const DmBlock b = A.blocks[blk];
+    const DmBlock b = load_block(A.blocks, blk);
     const int32_t corr = 128 * A.nchan;
 #pragma unroll 1
     for (int idx = tid; idx < TILE * 8; idx += 64 * W) {   // 4 samples x 1 trial per item
@@ -806,7 +822,7 @@ __device__ __forceinline__ void dedisp_quad_tile(const DedispArgs& A, int blk, i
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const DmBlock b = A.blocks[blk];
+    const DmBlock b = load_block(A.blocks, blk);
     const int nq = A.nchan_pad >> 2, count = b.count;
     const int64_t pitch = A.in_pitch;
     const int32_t n_in16 = static_cast<int32_t>(A.n_in16);
@@ -951,7 +967,7 @@ __device__ __forceinline__ void dedisp_quad_tile(const DedispArgs& A, int blk, i
 // Layout 6: the DM block's own step shape (the whole work-group takes one branch).
 template <int W, int TILE, int DEPTH, int MAXT>
 __device__ __forceinline__ void dedisp_mfma_mixed(const DedispArgs& A, int blk, int64_t t0) {
-    if (__builtin_amdgcn_readfirstlane(A.blocks[blk].cps) == 8)
+    if (__builtin_amdgcn_readfirstlane(load_block(A.blocks, blk).cps) == 8)
         dedisp_mfma_tile<W, TILE, DEPTH, MAXT, 8>(A, blk, t0);
     else
         dedisp_mfma_tile<W, TILE, DEPTH, MAXT, 4>(A, blk, t0);
@@ -998,6 +1014,9 @@ __global__ __launch_bounds__(64 * W, WPE) void dedisp_batch_kernel(const DedispA
             const int mid = (lo + hi + 1) >> 1;
             if (item_begin[mid] <= it) lo = mid; else hi = mid - 1;
         }
+        // the beam is the same in every lane; stating it keeps the beam's arguments and
+        // the tile's step records in scalar registers
+        lo = __builtin_amdgcn_readfirstlane(lo);
         const DedispArgs a = args[lo];
         const int64_t local = it - item_begin[lo];
         if constexpr (LAYOUT == 7)
