@@ -34,7 +34,7 @@ def harness(tmp_path_factory):
 
 # (time tile, staging chunks per step) of the quad variants, plus a tight budget that
 # forces short blocks
-@pytest.mark.parametrize("tile,chunks", [(1024, 32), (512, 16), (1024, 8)])
+@pytest.mark.parametrize("tile,chunks", [(1024, 32), (512, 16), (1024, 8), (2048, 64)])
 def test_quad_tables_reproduce_brute_force(harness, tile, chunks):
     r = subprocess.run([harness, str(tile), str(chunks)], capture_output=True, text=True, timeout=600)
     assert r.returncode == 0 and "ALL OK" in r.stdout, r.stdout + r.stderr
