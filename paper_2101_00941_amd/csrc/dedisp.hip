@@ -385,15 +385,15 @@ struct MfmaCtx {
     const DedispArgs* A;
     const uint8_t* recg;   // this DM block's records
     int64_t t0, last16;
-    int K, wave, lane, m, h, row, half, vlane, ps;
+    int K, wave, lane, m, h, row, ps;
     bool interior;         // every staged row of the tile lies inside [0, n_in16)
 };
 
 template <int TILE, int DEPTH, int MAXT, int CPS>
 struct MfmaLayout {
     static constexpr int ROW = mfma_row_bytes(MAXT);  // staged bytes per channel row
-    static constexpr int PARTS = ROW / 1024;          // staging waves per row
-    static constexpr int SW = CPS * PARTS;            // staging waves
+    static constexpr int PARTS = ROW / 1024;          // 1024-byte loads per staged row
+    static constexpr int SW = CPS;                    // staging waves, one per row
     static constexpr int STAGE = CPS * ROW;
     static constexpr MfmaRec RL = mfma_rec(CPS);      // record layout
     static constexpr int ACC = (TILE + 2) * 32 * 4;   // accumulator rows -1 .. TILE
@@ -416,37 +416,44 @@ struct MfmaNext {
     }
 };
 
-// Loads of step k into ring slot `slot`: each staging wave stages 1024 bytes of a
-// channel row (16 bytes per lane, `need` chunks of the row), then wave 0 the step's
-// record.
+// Loads of step k into ring slot `slot`: wave r < CPS stages channel row r of the step,
+// 1024 bytes per load (16 bytes per lane, `need` chunks of the row), then wave 0 the
+// step's record. The staging waves are the oldest of the work-group (waves w, w + 4, w +
+// 8, w + 12 share a SIMD, and older waves win issue), which wait longest at the step's
+// barrier; the youngest waves, whose chain sets the step's length, issue no loads and do
+// not queue behind the work-group's loads in the address unit.
 template <int TILE, int DEPTH, int MAXT, int CPS>
 __device__ __forceinline__ void mfma_issue(const MfmaCtx& cx, uint8_t* lds, const MfmaNext<CPS>& nx, int slot, int rs,
                                            int need) {
     using L = MfmaLayout<TILE, DEPTH, MAXT, CPS>;
     const DedispArgs& A = *cx.A;
     if (cx.wave >= L::SW) return;                      // waves 0 .. SW - 1 stage the rows
-    const int v = cx.vlane < need ? cx.vlane : 0;
-    uint8_t* dst = lds + L::RING + slot * L::STAGE + cx.row * L::ROW + cx.half * 1024;
     // plain pointer types keep the load builtins' arguments out of template dependence
     const uint8_t* rowp = nx.rowp;
     const uint8_t* recp = nx.recp;
-    if (nx.c < A.nchan) {
-        if (cx.interior) {
-            __builtin_amdgcn_global_load_lds(rowp + rs + 16 * v, (lds_void*)dst, 16, 0, 0);
-        } else {
-            const int64_t first = cx.t0 + rs;           // wave-uniform
-            const int top = need < 64 * cx.half + 64 ? need : 64 * cx.half + 64;
-            const uint8_t* row0 = rowp - cx.t0;         // the row at sample 0
-            if (first >= 0 && first + 16 * top <= A.n_in16) {
-                __builtin_amdgcn_global_load_lds(row0 + first + 16 * v, (lds_void*)dst, 16, 0, 0);
+#pragma unroll
+    for (int part = 0; part < L::PARTS; ++part) {
+        const int vlane = 64 * part + cx.lane;
+        const int v = vlane < need ? vlane : 0;
+        uint8_t* dst = lds + L::RING + slot * L::STAGE + cx.row * L::ROW + part * 1024;
+        if (nx.c < A.nchan) {
+            if (cx.interior) {
+                __builtin_amdgcn_global_load_lds(rowp + rs + 16 * v, (lds_void*)dst, 16, 0, 0);
             } else {
-                int64_t pos = first + 16 * v;
-                pos = pos < 0 ? 0 : (pos > cx.last16 ? cx.last16 : pos);
-                __builtin_amdgcn_global_load_lds(row0 + pos, (lds_void*)dst, 16, 0, 0);
+                const int64_t first = cx.t0 + rs;           // wave-uniform
+                const int top = need < 64 * part + 64 ? need : 64 * part + 64;
+                const uint8_t* row0 = rowp - cx.t0;         // the row at sample 0
+                if (first >= 0 && first + 16 * top <= A.n_in16) {
+                    __builtin_amdgcn_global_load_lds(row0 + first + 16 * v, (lds_void*)dst, 16, 0, 0);
+                } else {
+                    int64_t pos = first + 16 * v;
+                    pos = pos < 0 ? 0 : (pos > cx.last16 ? cx.last16 : pos);
+                    __builtin_amdgcn_global_load_lds(row0 + pos, (lds_void*)dst, 16, 0, 0);
+                }
             }
+        } else {
+            __builtin_amdgcn_global_load_lds(A.pad + 16 * v, (lds_void*)dst, 16, 0, 0);
         }
-    } else {
-        __builtin_amdgcn_global_load_lds(A.pad + 16 * v, (lds_void*)dst, 16, 0, 0);
     }
     if (cx.wave == 0) {
         uint8_t* rdst = lds + L::RECS + slot * L::RL.size;
@@ -464,7 +471,9 @@ __device__ __forceinline__ void mfma_issue(const MfmaCtx& cx, uint8_t* lds, cons
 template <int DEPTH>
 __device__ __forceinline__ void mfma_wait(const MfmaCtx& cx, int k) {
     if (k + DEPTH - 2 < cx.K) {
-        if (cx.ps == 2)
+        if (cx.ps == 3)
+            vmcnt_le<3 * (DEPTH - 2)>();
+        else if (cx.ps == 2)
             vmcnt_le<2 * (DEPTH - 2)>();
         else if (cx.ps == 1)
             vmcnt_le<DEPTH - 2>();
@@ -634,11 +643,10 @@ __device__ __forceinline__ void dedisp_mfma_tile(const DedispArgs& A, int blk, i
     cx.lane = tid & 63;
     cx.m = cx.lane & 31;
     cx.h = cx.lane >> 5;
-    // staging waves: row and 1024-byte part of the row; the others read row 0's entries
-    cx.row = cx.wave < L::SW ? cx.wave / L::PARTS : 0;
-    cx.half = cx.wave < L::SW ? cx.wave % L::PARTS : 0;
-    cx.vlane = 64 * cx.half + cx.lane;
-    cx.ps = cx.wave == 0 ? 2 : (cx.wave < L::SW ? 1 : 0);  // loads this wave issues per step
+    // staging waves: their row; the others read row 0's entries
+    cx.row = cx.wave < L::SW ? cx.wave : 0;
+    // loads this wave issues per step: its row's parts, and wave 0 the record
+    cx.ps = (cx.wave < L::SW ? L::PARTS : 0) + (cx.wave == 0 ? 1 : 0);
     const int32_t* rsv = A.base + static_cast<int64_t>(blk) * A.nchan_pad;
     {
         const DmBlock bk = load_block(A.blocks, blk);
