@@ -504,7 +504,8 @@ __device__ __forceinline__ void mfma_block(const MfmaCtx& cx, uint8_t* lds, int 
         constexpr bool FIRST = decltype(first)::value;
         const int rec = L::RECS + slot * L::RL.size;
         // every wave is done with the buffer of step k - 1: refill it with step k + DEPTH - 1
-        if (k + DEPTH - 1 < cx.K) {
+        // (the staging waves only: the others skip the refill's record reads as well)
+        if (k + DEPTH - 1 < cx.K && cx.wave < L::SW) {
             const int need = __builtin_amdgcn_readfirstlane(*reinterpret_cast<const int32_t*>(lds + rec + L::RL.next_need));
             const int rs = __builtin_amdgcn_readfirstlane(
                 *reinterpret_cast<const int32_t*>(lds + rec + L::RL.next_rs + 4 * cx.row));
