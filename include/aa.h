@@ -141,7 +141,11 @@ int aa_dedisperse(aa_plan_t plan, const uint8_t* d_in, int64_t in_pitch, int64_t
  *                                 and write the per-variant mean ms to ms_out
  *                                 [aa_variant_count()]; variants that cannot take the
  *                                 input (quad variants with in_pitch above 2^28) are
- *                                 skipped (-1). If AA_TUNE_CACHE names a file,
+ *                                 skipped (-1). For the mixed-shape variant (layout 6)
+ *                                 it also times the trial where the 4-channel blocks
+ *                                 start at 128 and 256 trials either side of the host's
+ *                                 estimate and keeps the fastest (ms_out holds that
+ *                                 time). If AA_TUNE_CACHE names a file,
  *                                 the choice is read from and written to that JSON
  *                                 cache, keyed by device arch and plan shape.
  * d_out receives the dedispersed plane of the last run.

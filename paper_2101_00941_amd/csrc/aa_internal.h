@@ -155,6 +155,7 @@ struct DedispTables {
     int32_t* d_base = nullptr;
     int32_t* d_offs = nullptr;
     uint8_t* d_pad = nullptr;        // layouts 4-6: one staged row of 0x80 bytes (padded channels)
+    int split = -1;                  // layout 6: first trial of the 4-channel blocks
 };
 
 // Arguments of one dedispersion launch (one beam), passed by value or from a device table.
@@ -204,7 +205,10 @@ int prepare_variant(aa_plan_s* p, int variant);
 // cps 4 or 8: one step shape; cps 0: 8 channels per step below a split trial and 4 from
 // it on, the split taken from a cost estimate, or split_at when that is >= 0.
 int build_mfma_tables(const aa_plan_s* p, int tile, int depth, int max_tiles, int cps, std::vector<DmBlock>& blocks,
-                      std::vector<int32_t>& rsv, std::vector<uint8_t>& rec, int split_at = -1);
+                      std::vector<int32_t>& rsv, std::vector<uint8_t>& rec, int split_at = -1, int* split_out = nullptr);
+// Rebuild the tables of a mixed-shape variant (layout 6) with its 4-channel blocks starting
+// at trial `split` (the autotuner's search around the host estimate).
+int prepare_mixed_split(aa_plan_s* p, int variant, int split);
 // Host tables of the quad variants: DM blocks (rec256 = first record, in 256-byte
 // units) and the records [block][nq + 1][quad_rec_dwords(chunks)].
 int build_quad_tables(const aa_plan_s* p, int tile, int chunks, std::vector<DmBlock>& blocks,

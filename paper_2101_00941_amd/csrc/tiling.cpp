@@ -218,7 +218,7 @@ double block_cost_ns(int cps, int64_t ntile, int K, int64_t tile_steps, int64_t 
 }  // namespace
 
 int build_mfma_tables(const aa_plan_s* p, int tile, int depth, int max_tiles, int cps, std::vector<DmBlock>& blocks,
-                      std::vector<int32_t>& rsv, std::vector<uint8_t>& rec, int split_at) {
+                      std::vector<int32_t>& rsv, std::vector<uint8_t>& rec, int split_at, int* split_out) {
     if (cps != 4 && cps != 8 && cps != 0) return fail(AA_EINVAL, "matrix-core tiling: 4, 8 or mixed channels per step");
     const MfmaGeom g{tile, depth, max_tiles, max_tiles * 32 - tile, mfma_row_bytes(max_tiles)};
     if (tile % 32 || tile < 256 || g.spread_max < 0 || depth < 3 || (max_tiles != 31 && max_tiles != 63))
@@ -261,6 +261,7 @@ int build_mfma_tables(const aa_plan_s* p, int tile, int depth, int max_tiles, in
             }
         }
     }
+    if (split_out) *split_out = split;
     blocks.clear();
     for (int d0 = 0; d0 < p->ndm;) {
         const int shape = d0 < split ? 8 : 4;
@@ -439,12 +440,12 @@ int prepare_quad(const aa_plan_s* p, const DedispVariant& V, DedispTables& t) {
     return AA_OK;
 }
 
-int prepare_mfma(const aa_plan_s* p, const DedispVariant& V, DedispTables& t) {
+int prepare_mfma(const aa_plan_s* p, const DedispVariant& V, DedispTables& t, int split_at = -1) {
     std::vector<DmBlock> blocks;
     std::vector<int32_t> rsv;
     std::vector<uint8_t> rec;
     const int cps = mfma_cps(V.layout);   // 0: mixed by trial range
-    const int rc0 = build_mfma_tables(p, V.tile, V.depth, V.max_tiles, cps, blocks, rsv, rec);
+    const int rc0 = build_mfma_tables(p, V.tile, V.depth, V.max_tiles, cps, blocks, rsv, rec, split_at, &t.split);
     if (rc0 != AA_OK) return rc0;
     t.bd = 32;
     t.nchan_pad = cps == 4 ? (p->nchan + 3) / 4 * 4 : (p->nchan + 7) / 8 * 8;
@@ -461,6 +462,21 @@ int prepare_mfma(const aa_plan_s* p, const DedispVariant& V, DedispTables& t) {
     return AA_OK;
 }
 }  // namespace
+
+int prepare_mixed_split(aa_plan_s* p, int v, int split) {
+    if (v < 0 || v >= kNumDedispVariants || kDedispVariants[v].layout != 6)
+        return fail(AA_EINVAL, "prepare_mixed_split: not a mixed-shape variant");
+    DedispTables t;
+    t.variant = v;
+    const int rc = prepare_mfma(p, kDedispVariants[v], t, std::max(0, std::min(split, p->ndm)));
+    if (rc != AA_OK) {
+        free_tables(t);
+        return rc;
+    }
+    free_tables(p->tables[v]);
+    p->tables[v] = t;
+    return AA_OK;
+}
 
 int prepare_variant(aa_plan_s* p, int v) {
     if (v < 0 || v >= kNumDedispVariants) return fail(AA_EINVAL, "unknown dedispersion variant");

@@ -3,6 +3,7 @@
 // budget. The tuner times each variant with HIP events on the caller's stream and
 // keeps the fastest. A flat JSON cache, named by AA_TUNE_CACHE, remembers the
 // choice per (arch, plan shape).
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <fstream>
@@ -105,7 +106,11 @@ extern "C" int aa_autotune(aa_plan_t p, const uint8_t* d_in, int64_t in_pitch, i
         const auto m = read_cache(cache);
         const auto it = m.find(key);
         if (it != m.end() && it->second >= 0 && it->second < kNumDedispVariants) {
-            const int rc = aa_plan_set_variant(p, it->second);
+            int rc = aa_plan_set_variant(p, it->second);
+            const auto sp = m.find(key + "|split");
+            if (rc == AA_OK && sp != m.end() && kDedispVariants[it->second].layout == 6 &&
+                sp->second != p->tables[it->second].split)
+                rc = prepare_mixed_split(p, it->second, sp->second);
             if (rc == AA_OK && ms_out)
                 for (int v = 0; v < kNumDedispVariants; ++v) ms_out[v] = -1.0f;
             if (rc == AA_OK) return aa_dedisperse(p, d_in, in_pitch, n_in, d_out, out_pitch, stream_);
@@ -117,23 +122,51 @@ extern "C" int aa_autotune(aa_plan_t p, const uint8_t* d_in, int64_t in_pitch, i
     int best = -1;
     float best_ms = 0;
     int rc = AA_OK;
+    // one warm-up and `reps` timed launches of the variant's current tables
+    auto time_variant = [&](int v, float& ms) {
+        int r = launch_dedisperse(p, v, d_in, in_pitch, n_in, d_out, out_pitch, stream);  // warm-up
+        if (r != AA_OK) return r;
+        (void)hipEventRecord(e0, stream);
+        for (int i = 0; i < reps && r == AA_OK; ++i) r = launch_dedisperse(p, v, d_in, in_pitch, n_in, d_out, out_pitch, stream);
+        (void)hipEventRecord(e1, stream);
+        if (r != AA_OK) return r;
+        const hipError_t e = hipEventSynchronize(e1);
+        if (e != hipSuccess) return hip_fail(e, "aa_autotune: hipEventSynchronize");
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        ms /= static_cast<float>(reps);
+        return AA_OK;
+    };
     for (int v = 0; v < kNumDedispVariants; ++v) {
         float ms = -1.0f;
         if (variant_takes_pitch(v, in_pitch) && prepare_variant(p, v) == AA_OK) {
-            rc = launch_dedisperse(p, v, d_in, in_pitch, n_in, d_out, out_pitch, stream);  // warm-up
+            rc = time_variant(v, ms);
             if (rc != AA_OK) break;
-            (void)hipEventRecord(e0, stream);
-            for (int r = 0; r < reps && rc == AA_OK; ++r)
-                rc = launch_dedisperse(p, v, d_in, in_pitch, n_in, d_out, out_pitch, stream);
-            (void)hipEventRecord(e1, stream);
-            if (rc != AA_OK) break;
-            const hipError_t e = hipEventSynchronize(e1);
-            if (e != hipSuccess) {
-                rc = hip_fail(e, "aa_autotune: hipEventSynchronize");
-                break;
+            if (kDedispVariants[v].layout == 6) {
+                // mixed step shapes: also time splits around the host's estimate, in steps of
+                // 128 and 256 trials, and keep the fastest
+                const int s0 = p->tables[v].split;
+                int best_split = s0, cand[4], nc = 0;
+                for (int delta : {-256, -128, 128, 256}) {
+                    const int s = std::max(0, std::min(s0 + delta, p->ndm));
+                    bool seen = s == s0;
+                    for (int i = 0; i < nc; ++i) seen = seen || cand[i] == s;
+                    if (!seen) cand[nc++] = s;
+                }
+                for (int i = 0; i < nc; ++i) {
+                    const int s = cand[i];
+                    float m = -1.0f;
+                    rc = prepare_mixed_split(p, v, s);
+                    if (rc == AA_OK) rc = time_variant(v, m);
+                    if (rc != AA_OK) break;
+                    if (m < ms) {
+                        ms = m;
+                        best_split = s;
+                    }
+                }
+                if (rc != AA_OK) break;
+                if (best_split != p->tables[v].split) rc = prepare_mixed_split(p, v, best_split);
+                if (rc != AA_OK) break;
             }
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            ms /= static_cast<float>(reps);
             if (best < 0 || ms < best_ms) {
                 best = v;
                 best_ms = ms;
@@ -150,6 +183,7 @@ extern "C" int aa_autotune(aa_plan_t p, const uint8_t* d_in, int64_t in_pitch, i
         std::lock_guard<std::mutex> g(g_cache_mu);
         auto m = read_cache(cache);
         m[key] = best;
+        if (kDedispVariants[best].layout == 6) m[key + "|split"] = p->tables[best].split;
         write_cache(cache, m);
     }
     return launch_dedisperse(p, best, d_in, in_pitch, n_in, d_out, out_pitch, stream);

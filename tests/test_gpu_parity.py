@@ -91,7 +91,10 @@ def test_autotune_selects_a_variant_and_stays_exact(tmp_path, monkeypatch):
     q = _plan(nchan, nsamp, 1450.0, 300.0 / nchan, 64e-6, dms, [1], 1e9)
     ms2 = q.autotune(xd, n_in=nsamp, reps=1)
     assert all(m == -1.0 for m in ms2) and q.variant == p.variant
-    assert '"' in (tmp_path / "tune.json").read_text()
+    text = (tmp_path / "tune.json").read_text()
+    assert '"' in text
+    # a mixed-shape pick stores its tuned split next to the variant
+    assert ("|split" in text) == (Plan.variants()[p.variant]["layout"] == 6)
 
 
 def test_dedisp_saturated_input_exact():
