@@ -55,8 +55,8 @@ I8_MFMA_PEAK_TOPS = 5000.0
 # the kernel sources the counters were taken on: after any change to those sources the
 # entry no longer matches and the bench reports traffic as null.
 TRAFFIC_BYTES = {
-    ("survey_4096ch_1M", 20): (190.28e9 + 12.15e9, "e219a898ff2dbf8a"),
-    ("survey_4096ch_1M", 23): (464.86e9 + 12.15e9, "e219a898ff2dbf8a"),
+    ("survey_4096ch_1M", 20): (196.62e9 + 12.15e9, "2a64072bc06edccd"),
+    ("survey_4096ch_1M", 23): (466.86e9 + 12.15e9, "2a64072bc06edccd"),
 }
 KERNEL_SOURCES = ("dedisp.hip", "tiling.cpp", "aa_internal.h", "xcd.h")
 # the part of aa_internal.h that the dedispersion kernels use: tiling constants, variant

@@ -385,7 +385,7 @@ struct MfmaCtx {
     const DedispArgs* A;
     const uint8_t* recg;   // this DM block's records
     int64_t t0, last16;
-    int K, wave, lane, m, h, row, ps;
+    int K, wave, lane, m, h, row, part0, ps;
     bool interior;         // every staged row of the tile lies inside [0, n_in16)
 };
 
@@ -393,7 +393,11 @@ template <int TILE, int DEPTH, int MAXT, int CPS>
 struct MfmaLayout {
     static constexpr int ROW = mfma_row_bytes(MAXT);  // staged bytes per channel row
     static constexpr int PARTS = ROW / 1024;          // 1024-byte loads per staged row
-    static constexpr int SW = CPS;                    // staging waves, one per row
+    // staging waves per row: two for 4-channel steps with 2048-byte rows (waves 0-7, one
+    // load each), else one (waves 0-7 stage the 8-channel steps' rows, two loads each)
+    static constexpr int SPLIT = (CPS == 4 && PARTS == 2) ? 2 : 1;
+    static constexpr int LPW = PARTS / SPLIT;                        // loads per staging wave
+    static constexpr int SW = CPS * SPLIT;            // staging waves
     static constexpr int STAGE = CPS * ROW;
     static constexpr MfmaRec RL = mfma_rec(CPS);      // record layout
     static constexpr int ACC = (TILE + 2) * 32 * 4;   // accumulator rows -1 .. TILE
@@ -416,12 +420,13 @@ struct MfmaNext {
     }
 };
 
-// Loads of step k into ring slot `slot`: wave r < CPS stages channel row r of the step,
-// 1024 bytes per load (16 bytes per lane, `need` chunks of the row), then wave 0 the
-// step's record. The staging waves are the oldest of the work-group (waves w, w + 4, w +
-// 8, w + 12 share a SIMD, and older waves win issue), which wait longest at the step's
-// barrier; the youngest waves, whose chain sets the step's length, issue no loads and do
-// not queue behind the work-group's loads in the address unit.
+// Loads of step k into ring slot `slot`: the staging waves (L::SW of them, L::SPLIT per
+// row) each load L::LPW 1024-byte parts of their row (16 bytes per lane, `need` chunks of
+// the row), then wave 0 the step's record. The staging waves are the oldest of the
+// work-group (waves w, w + 4, w + 8, w + 12 share a SIMD, and older waves win issue),
+// which wait longest at the step's barrier; the youngest waves, whose chain sets the
+// step's length, issue no loads and do not queue behind the work-group's loads in the
+// address unit.
 template <int TILE, int DEPTH, int MAXT, int CPS>
 __device__ __forceinline__ void mfma_issue(const MfmaCtx& cx, uint8_t* lds, const MfmaNext<CPS>& nx, int slot, int rs,
                                            int need) {
@@ -432,7 +437,8 @@ __device__ __forceinline__ void mfma_issue(const MfmaCtx& cx, uint8_t* lds, cons
     const uint8_t* rowp = nx.rowp;
     const uint8_t* recp = nx.recp;
 #pragma unroll
-    for (int part = 0; part < L::PARTS; ++part) {
+    for (int pi = 0; pi < L::LPW; ++pi) {
+        const int part = cx.part0 + pi;
         const int vlane = 64 * part + cx.lane;
         const int v = vlane < need ? vlane : 0;
         uint8_t* dst = lds + L::RING + slot * L::STAGE + cx.row * L::ROW + part * 1024;
@@ -645,9 +651,10 @@ __device__ __forceinline__ void dedisp_mfma_tile(const DedispArgs& A, int blk, i
     cx.m = cx.lane & 31;
     cx.h = cx.lane >> 5;
     // staging waves: their row; the others read row 0's entries
-    cx.row = cx.wave < L::SW ? cx.wave : 0;
+    cx.row = cx.wave < L::SW ? cx.wave / L::SPLIT : 0;
+    cx.part0 = cx.wave < L::SW ? (cx.wave % L::SPLIT) * L::LPW : 0;
     // loads this wave issues per step: its row's parts, and wave 0 the record
-    cx.ps = (cx.wave < L::SW ? L::PARTS : 0) + (cx.wave == 0 ? 1 : 0);
+    cx.ps = (cx.wave < L::SW ? L::LPW : 0) + (cx.wave == 0 ? 1 : 0);
     const int32_t* rsv = A.base + static_cast<int64_t>(blk) * A.nchan_pad;
     {
         const DmBlock bk = load_block(A.blocks, blk);
