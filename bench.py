@@ -220,6 +220,11 @@ def stream_run(plan, src, nsamp, chunk, S, serial=False, sdma=False, staged=Fals
 
 
 def _stream_rows(plan, host, nsamp, chunk, modes, budget, cap, src_cols=None, pageable=None, min_piece_work=0):
+    # one untimed pass of every mode first: the first multi-stream pipelines of a process
+    # ran slower than the same configuration later in it
+    for mode, S, serial, sdma, is_pageable, staged in modes:
+        stream_run(plan, pageable if is_pageable else host, nsamp, chunk, S, serial, sdma, staged, budget, cap,
+                   src_cols, reps=1, min_piece_work=min_piece_work)
     rows = []
     for mode, S, serial, sdma, is_pageable, staged in modes:
         src = pageable if is_pageable else host
