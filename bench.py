@@ -114,7 +114,7 @@ def cpu_baseline(w, x, threads=None, groups=None, rows_per_group=4):
     import oracle
     ncpu = os.cpu_count() or 1
     threads = threads or max(1, min(16, ncpu))
-    groups = groups or threads
+    groups = groups or 2 * threads   # about 10 s on 16 host threads
     ndm = len(w["dms"])
     step = ndm // groups
     starts = [min(max(1, step // 2 + k * step), ndm - rows_per_group - 1) for k in range(groups)]
