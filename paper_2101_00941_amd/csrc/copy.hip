@@ -49,7 +49,7 @@ int launch_gather_rows(uint8_t* dst, int64_t dpitch, const uint8_t* src, int64_t
     const int64_t want = (total + 256 * 4 - 1) / (256 * 4);
     // The copy is bound by PCIe reads of mapped host memory, not by the CUs: 32 work-groups
     // of 4 waves, each lane with 4 x 16 bytes in flight, keep 512 KB of reads outstanding,
-    // which holds the full host-link rate (measured: 57 GB/s from 24 to 160 work-groups,
+    // which holds the full host-link rate (measured: 56 GB/s from 24 to 160 work-groups,
     // slower at 16), and leave the other CUs to the kernels it overlaps. At 160 work-groups
     // the overlapped dedispersion launches ran 3.5-5x longer than alone.
     const unsigned grid = static_cast<unsigned>(std::min<int64_t>(want, 32));
